@@ -1,0 +1,140 @@
+/*
+ * jk.h -- C-ABI of the AO-direct J/K build for AMD MI355X (gfx950).
+ *
+ * The library computes, for a batch of nd real (generally non-symmetric)
+ * densities D^x over a basis of contracted s/p/d Gaussian shells,
+ *
+ *   J^x_{mn} = sum_{ls} (mn|ls) D^x_{ls},    K^x_{mn} = sum_{ls} (ml|ns) D^x_{ls}
+ *
+ * (paper Sect. 2.2, Eq. (jkbuild)).  Two-electron integrals are generated on
+ * the fly on the GPU and never stored beyond a bounded work buffer; no
+ * four-index tensor is allocated.  Builds are bare: no factor 1/2, no spin
+ * factor, no 2J-K (Sect. 2, "Notation and conventions").  K uses the whole D:
+ * its antisymmetric part is never dropped (Sect. 2.4); J depends only on
+ * (D + D^T)/2, which follows from (mn|ls) = (mn|sl).  Pure d functions enter at
+ * matrix level, D_cart = T D T^T and J = T^T J_cart T (Sect. 3,
+ * screening-robustness paragraph), so the kernels stay Cartesian.
+ *
+ * Screening (Sect. 2.2, "Cost": O(N^2) once Schwarz screening is applied): a
+ * canonical shell quartet (ab|cd) is evaluated iff Q_ab Q_cd >= tol and
+ * Q_ab Q_cd * Dmax >= tol, with Q_ab = sqrt(max_{m in a, n in b} (mn|mn)) over
+ * Cartesian functions and Dmax the largest |D_cart| over the batch in the six
+ * shell-pair blocks ab, cd, ac, ad, bc, bd.
+ *
+ * Conventions of a basis.  Coefficients multiply primitives normalized on
+ * their x^l component; the library rescales each contraction to unit x^l
+ * self-overlap.  Function order within a shell: p = (x, y, z); Cartesian d =
+ * (xx, xy, xz, yy, yz, zz); pure d = (xy, yz, 3z^2-r^2, xz, x^2-y^2), each
+ * of unit self-overlap.  Matrices are row-major, D[x][l][s] = D^x_{ls}.
+ *
+ * Errors.  Every entry point returns JK_OK or a negative code and never
+ * throws; jk_last_error() gives a message for the calling thread.  Kernel
+ * faults are asynchronous: they surface at the next synchronizing call on
+ * the stream.
+ */
+#ifndef JK_H
+#define JK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JK_OK 0
+#define JK_EINVAL (-1)       /* bad descriptor or argument */
+#define JK_ENOMEM (-2)       /* device memory for the request can never fit */
+#define JK_EDEVICE (-3)      /* HIP runtime error; message has the detail */
+#define JK_EUNSUPPORTED (-4) /* valid request outside what this build supports */
+
+#define JK_MAX_L 2           /* s, p, d */
+#define JK_MAX_PRIM 16       /* primitives per shell */
+
+#define JK_FP64 0            /* every quartet in FP64 */
+#define JK_MIXED 1           /* quartets with Q_ab Q_cd < fp32_bound in FP32, FP64 accumulation */
+
+typedef struct jk_basis_s* jk_basis_t; /* opaque; owned by the library */
+
+/* Basis descriptor.  All pointers are host memory, read during
+ * jk_create_basis only. */
+typedef struct {
+    int32_t natoms;
+    const double* xyz;          /* [natoms*3], bohr */
+    int32_t nshells;
+    const int32_t* shell_atom;  /* [nshells], 0..natoms-1 */
+    const int32_t* shell_l;     /* [nshells], 0..JK_MAX_L */
+    const int32_t* shell_nprim; /* [nshells], 1..JK_MAX_PRIM */
+    const double* exps;         /* concatenated per shell, > 0 and finite */
+    const double* coefs;        /* concatenated per shell, finite */
+    int32_t spherical;          /* 1: pure d (5 functions); 0: Cartesian d (6) */
+} jk_basis_desc;
+
+/* Build options; jk_default_opts() fills the defaults. */
+typedef struct {
+    int32_t precision;      /* JK_FP64 (default) or JK_MIXED */
+    double schwarz_tol;     /* screening threshold tol, default 1e-12; >= 0 */
+    double fp32_bound;      /* JK_MIXED: Q_ab Q_cd below this -> FP32, default 1e-6 */
+    int32_t want_j;         /* default 1 */
+    int32_t want_k;         /* default 1 */
+    int32_t symmetric_hint; /* reserved, must be 0 or 1; results never depend on it */
+    void* stream;           /* hipStream_t for all work of the call; NULL = default stream */
+    void* workspace;        /* optional device buffer of >= jk_workspace_bytes();
+                               NULL: the library allocates stream-ordered memory */
+    size_t workspace_bytes; /* size of `workspace` */
+} jk_build_opts;
+
+void jk_default_opts(jk_build_opts* o);
+
+/* Ingest a basis on the current HIP device: validates the descriptor,
+ * normalizes contractions, builds the resident shell-pair data, Schwarz
+ * factors and screened quartet lists.  Synchronous.  On success *out owns
+ * device memory until jk_destroy.  JK_EINVAL for an invalid descriptor
+ * (l > JK_MAX_L, nprim outside 1..JK_MAX_PRIM, exponent <= 0 or non-finite,
+ * NULL arrays, shell_atom out of range). */
+int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out);
+
+/* Number of basis functions n of the D/J/K matrices (pure or Cartesian). */
+int jk_nbf(jk_basis_t h);
+
+/* J and K for nd densities.  D, J, K are device pointers to row-major
+ * [nd][n][n] FP64 arrays (n = jk_nbf); J and K are overwritten.  The caller
+ * owns D, J, K and the stream; D must stay valid, and J/K untouched, until
+ * the stream has passed the call.  Asynchronous on o->stream.  Either output
+ * may be NULL when the matching want_ flag is 0.  Re-entrant: one handle may
+ * be used concurrently on several streams, each call with its own workspace.
+ * JK_EINVAL for nd < 1, NULL pointers, tol < 0 or an unknown precision;
+ * JK_ENOMEM when the workspace cannot be obtained. */
+int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
+             const jk_build_opts* o);
+
+/* Device bytes one jk_build call with nd densities needs as workspace. */
+size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o);
+
+/* Release everything the handle owns.  NULL-safe.  The caller must have
+ * synchronized every stream that used the handle. */
+void jk_destroy(jk_basis_t h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* jk_last_error(void);
+
+/* Canonical shell quartets kept by the Schwarz part of the screen at
+ * tolerance tol (the density part is applied per call). */
+int64_t jk_quartet_count(jk_basis_t h, double tol);
+
+/* Statistics of the most recent jk_build on this handle (host values):
+ * out[0] quartets evaluated (after density screening), out[1] of them in
+ * FP32, out[2] Cartesian function quartets, out[3] primitive quartets,
+ * out[4] algorithmic ERI flops, out[5] algorithmic digestion flops. */
+int jk_last_stats(jk_basis_t h, double out[6]);
+
+/* Contracted, normalized Cartesian ERI tiles (ab|cd) for nq shell quartets
+ * given as user shell indices shells[4*i .. 4*i+3] (host memory).  out
+ * (host) receives the tiles back to back, each [na][nb][nc][nd] in Cartesian
+ * component order.  For tests of the integral kernels.  Synchronous. */
+int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JK_H */

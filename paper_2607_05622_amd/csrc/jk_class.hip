@@ -1,0 +1,138 @@
+// One canonical shell-quartet class per translation unit: compiled once per
+// class index with -DJK_CLASS_INDEX=n so the generated recurrences build in
+// parallel.  Defines launch_eri_tile_c<n> and launch_digest_c<n>.
+#include "jk_device.h"
+
+#ifndef JK_CLASS_INDEX
+#error "compile with -DJK_CLASS_INDEX=<0..20>"
+#endif
+
+namespace jk {
+
+#define JK_PASTE2(a, b) a##b
+#define JK_PASTE(a, b) JK_PASTE2(a, b)
+
+#define JK_DEFINE(idx, tag, la, lb, lc, ld)                                                       \
+    static_assert(idx >= 0, "");                                                                  \
+    hipError_t JK_PASTE(launch_eri_tile_c, idx)(const EriTileArgs& a, hipStream_t s) {            \
+        const unsigned g = static_cast<unsigned>((a.nq + 255) / 256);                             \
+        hipLaunchKernelGGL(k_eri_tile<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);            \
+        return hipGetLastError();                                                                 \
+    }                                                                                             \
+    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s) {               \
+        const int per = 256 / a.dg;                                                               \
+        const unsigned g = static_cast<unsigned>((a.nq + per - 1) / per);                         \
+        hipLaunchKernelGGL((k_digest<la, lb, lc, ld>), dim3(g), dim3(256), 0, s, a);              \
+        return hipGetLastError();                                                                 \
+    }
+
+#define JK_SELECT(idx, tag, la, lb, lc, ld) JK_SELECT_##idx(idx, tag, la, lb, lc, ld)
+#if JK_CLASS_INDEX == 0
+#define JK_SELECT_0(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_0(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 1
+#define JK_SELECT_1(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_1(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 2
+#define JK_SELECT_2(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_2(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 3
+#define JK_SELECT_3(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_3(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 4
+#define JK_SELECT_4(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_4(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 5
+#define JK_SELECT_5(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_5(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 6
+#define JK_SELECT_6(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_6(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 7
+#define JK_SELECT_7(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_7(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 8
+#define JK_SELECT_8(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_8(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 9
+#define JK_SELECT_9(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_9(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 10
+#define JK_SELECT_10(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_10(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 11
+#define JK_SELECT_11(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_11(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 12
+#define JK_SELECT_12(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_12(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 13
+#define JK_SELECT_13(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_13(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 14
+#define JK_SELECT_14(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_14(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 15
+#define JK_SELECT_15(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_15(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 16
+#define JK_SELECT_16(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_16(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 17
+#define JK_SELECT_17(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_17(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 18
+#define JK_SELECT_18(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_18(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 19
+#define JK_SELECT_19(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_19(idx, tag, la, lb, lc, ld)
+#endif
+#if JK_CLASS_INDEX == 20
+#define JK_SELECT_20(idx, tag, la, lb, lc, ld) JK_DEFINE(idx, tag, la, lb, lc, ld)
+#else
+#define JK_SELECT_20(idx, tag, la, lb, lc, ld)
+#endif
+
+JK_CLASS_LIST(JK_SELECT)
+
+}  // namespace jk

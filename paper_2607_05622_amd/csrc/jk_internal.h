@@ -1,0 +1,55 @@
+// Internal data layout shared by the host side and the kernels of the J/K
+// library.  Nothing here is part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jk {
+
+constexpr int kMaxL = 2;
+constexpr int kNumPairClass = 6;    // ss ps pp ds dp dd
+constexpr int kNumClass = 21;       // canonical (la lb | lc ld)
+
+// Boys table: F_m(T0) for m = 0..kBoysCols-2 and exp(-T0) in the last
+// column, at T0 = i / kBoysInvStep for T0 < kBoysTMax.
+constexpr int kBoysCols = 16;
+constexpr double kBoysInvStep = 32.0;
+constexpr double kBoysTMax = 50.0;
+constexpr int kBoysPoints = 1601;   // 0 .. 50 inclusive at 1/32
+
+// One shell pair (a >= b in internal shell order, so la >= lb).
+struct PairInfo {
+    double A[3];      // centre of a
+    double AB[3];     // A - B
+    double q;         // Schwarz factor sqrt(max (mn|mn))
+    int32_t prim_off; // first primitive-pair record
+    int32_t nprim;    // number of primitive-pair records
+    int32_t sa, sb;   // internal shells
+    int32_t fa, fb;   // first internal Cartesian function of a, b
+};
+
+// One primitive pair of a shell pair: p = alpha + beta, P = (alpha A +
+// beta B)/p, E = sqrt(2) pi^(5/4) c_a c_b exp(-alpha beta/p |AB|^2) / p (so
+// that the primitive-quartet prefactor 2 pi^(5/2) K_ab K_cd / (p q
+// sqrt(p+q)) is E_ab E_cd / sqrt(p+q)), o2p = 1/(2p).
+struct PrimPair {
+    double p, P[3], E, o2p, pad0, pad1;
+};
+
+// Per-primitive-quartet coefficients of the vertical recurrence.
+template <typename R>
+struct VrrCoef {
+    R PA[3], WP[3], QC[3], WQ[3];
+    R rp, rq;          // rho/p, rho/q
+    R o2p, o2q, o2pq;  // 1/2p, 1/2q, 1/2(p+q)
+};
+
+// Canonical class index of (la lb | lc ld) with la >= lb, lc >= ld and
+// pair class(la,lb) >= pair class(lc,ld).
+__host__ __device__ inline int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
+__host__ __device__ inline int quartet_class(int X, int Y) { return X * (X + 1) / 2 + Y; }
+
+inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+}  // namespace jk

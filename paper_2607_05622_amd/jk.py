@@ -1,0 +1,247 @@
+"""Python binding of the J/K C-ABI (include/jk.h): argument marshalling only.
+
+Every step of a build runs in the HIP library ``libjk.so`` built next to this
+file; there is no fallback.  If the library is missing this module raises on
+first use.  Functions keep the C names; ``JKBasis`` is a small owner of a
+handle.  Device arrays are torch tensors (``cuda``, float64, contiguous),
+used only as memory and stream carriers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "jk.h")
+
+JK_OK, JK_EINVAL, JK_ENOMEM, JK_EDEVICE, JK_EUNSUPPORTED = 0, -1, -2, -3, -4
+JK_FP64, JK_MIXED = 0, 1
+
+
+class JKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jk error {code}: {msg}")
+        self.code = code
+
+
+class jk_basis_desc(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int32), ("xyz", ctypes.POINTER(ctypes.c_double)),
+                ("nshells", ctypes.c_int32), ("shell_atom", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_l", ctypes.POINTER(ctypes.c_int32)), ("shell_nprim", ctypes.POINTER(ctypes.c_int32)),
+                ("exps", ctypes.POINTER(ctypes.c_double)), ("coefs", ctypes.POINTER(ctypes.c_double)),
+                ("spherical", ctypes.c_int32)]
+
+
+class jk_build_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("schwarz_tol", ctypes.c_double),
+                ("fp32_bound", ctypes.c_double), ("want_j", ctypes.c_int32), ("want_k", ctypes.c_int32),
+                ("symmetric_hint", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libjk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp, c_int, c_i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    lib.jk_default_opts.argtypes = [ctypes.POINTER(jk_build_opts)]
+    lib.jk_default_opts.restype = None
+    lib.jk_create_basis.argtypes = [ctypes.POINTER(jk_basis_desc), ctypes.POINTER(vp)]
+    lib.jk_create_basis.restype = c_int
+    lib.jk_nbf.argtypes = [vp]
+    lib.jk_nbf.restype = c_int
+    lib.jk_build.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts)]
+    lib.jk_build.restype = c_int
+    lib.jk_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(jk_build_opts)]
+    lib.jk_workspace_bytes.restype = ctypes.c_size_t
+    lib.jk_destroy.argtypes = [vp]
+    lib.jk_destroy.restype = None
+    lib.jk_last_error.argtypes = []
+    lib.jk_last_error.restype = ctypes.c_char_p
+    lib.jk_quartet_count.argtypes = [vp, ctypes.c_double]
+    lib.jk_quartet_count.restype = c_i64
+    lib.jk_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.jk_last_stats.restype = c_int
+    lib.jk_eri_tiles.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.jk_eri_tiles.restype = c_int
+    _lib = lib
+    return lib
+
+
+def declared_functions(header: str = HEADER) -> list[str]:
+    """Names of the functions include/jk.h declares."""
+    txt = open(header).read()
+    return sorted(set(re.findall(r"\b(jk_[a-z_]+)\s*\(", txt)))
+
+
+def jk_last_error() -> str:
+    return load().jk_last_error().decode()
+
+
+def _check(rc):
+    if rc != JK_OK:
+        raise JKError(rc, jk_last_error())
+
+
+def jk_default_opts(**kw) -> jk_build_opts:
+    o = jk_build_opts()
+    load().jk_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _desc(arrays: dict):
+    keep = dict(
+        xyz=np.ascontiguousarray(arrays["xyz"], dtype=np.float64).reshape(-1),
+        shell_atom=np.ascontiguousarray(arrays["shell_atom"], dtype=np.int32),
+        shell_l=np.ascontiguousarray(arrays["shell_l"], dtype=np.int32),
+        shell_nprim=np.ascontiguousarray(arrays["shell_nprim"], dtype=np.int32),
+        exps=np.ascontiguousarray(arrays["exps"], dtype=np.float64),
+        coefs=np.ascontiguousarray(arrays["coefs"], dtype=np.float64))
+    d = jk_basis_desc()
+    d.natoms = int(arrays["natoms"])
+    d.nshells = int(arrays["nshells"])
+    d.spherical = int(arrays["spherical"])
+    for k in ("xyz", "exps", "coefs"):
+        setattr(d, k, keep[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    for k in ("shell_atom", "shell_l", "shell_nprim"):
+        setattr(d, k, keep[k].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return d, keep
+
+
+def jk_create_basis(basis) -> int:
+    """Returns the opaque handle as an integer; ``basis`` is a synth.Basis or
+    a dict with the descriptor's arrays."""
+    arrays = basis.as_arrays() if hasattr(basis, "as_arrays") else basis
+    d, keep = _desc(arrays)
+    h = ctypes.c_void_p()
+    _check(load().jk_create_basis(ctypes.byref(d), ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def jk_nbf(h) -> int:
+    n = load().jk_nbf(h)
+    if n < 0:
+        _check(n)
+    return n
+
+
+def jk_destroy(h) -> None:
+    load().jk_destroy(h)
+
+
+def jk_quartet_count(h, tol: float = 1e-12) -> int:
+    n = load().jk_quartet_count(h, tol)
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def jk_last_stats(h) -> dict:
+    out = (ctypes.c_double * 6)()
+    _check(load().jk_last_stats(h, out))
+    keys = ["quartets", "quartets_fp32", "function_quartets", "primitive_quartets", "eri_flops", "digest_flops"]
+    return dict(zip(keys, list(out)))
+
+
+def jk_workspace_bytes(h, nd: int, opts: jk_build_opts | None = None) -> int:
+    return int(load().jk_workspace_bytes(h, nd, ctypes.byref(opts) if opts is not None else None))
+
+
+def _dev_ptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 cuda tensor")
+    if t.dim() != 3 or t.shape[1] != n or t.shape[2] != n:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [nd, {n}, {n}]")
+    return t.data_ptr()
+
+
+def jk_build(h, D, J=None, K=None, opts: jk_build_opts | None = None, stream=None):
+    """J and K of the densities D[nd, n, n] (torch cuda float64).  Output
+    tensors are allocated when not given.  Runs on ``stream`` (a
+    torch.cuda.Stream) or torch's current stream."""
+    import torch
+    n = jk_nbf(h)
+    if D.dim() == 2:
+        D = D.unsqueeze(0)
+    nd = D.shape[0]
+    o = opts if opts is not None else jk_default_opts()
+    if J is None and o.want_j:
+        J = torch.empty_like(D)
+    if K is None and o.want_k:
+        K = torch.empty_like(D)
+    s = stream if stream is not None else torch.cuda.current_stream(D.device)
+    o.stream = ctypes.c_void_p(s.cuda_stream)
+    dp = _dev_ptr(D, n, "D")
+    jp = _dev_ptr(J, n, "J") if o.want_j else None
+    kp = _dev_ptr(K, n, "K") if o.want_k else None
+    _check(load().jk_build(h, nd, dp, jp, kp, ctypes.byref(o)))
+    return J, K
+
+
+def jk_eri_tiles(h, shells, shell_l) -> list:
+    """Cartesian ERI tiles for user shell quartets [(a, b, c, d), ...];
+    ``shell_l`` gives each user shell's angular momentum (tile sizes)."""
+    sh = np.ascontiguousarray(np.asarray(shells, dtype=np.int32).reshape(-1, 4))
+    l = np.asarray(shell_l)
+    nc = (l + 1) * (l + 2) // 2
+    sizes = [int(np.prod([nc[s] for s in q])) for q in sh]
+    out = np.zeros(max(sum(sizes), 1))
+    _check(load().jk_eri_tiles(h, len(sh), sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    res, off = [], 0
+    for q, s in zip(sh, sizes):
+        res.append(out[off:off + s].reshape([int(nc[x]) for x in q]))
+        off += s
+    return res
+
+
+class JKBasis:
+    """Owner of one library handle."""
+
+    def __init__(self, basis):
+        self.basis = basis
+        self.h = jk_create_basis(basis)
+        self.nbf = jk_nbf(self.h)
+
+    def build(self, D, J=None, K=None, **opts):
+        o = jk_default_opts(**opts) if opts else None
+        return jk_build(self.h, D, J, K, o)
+
+    def eri_tiles(self, shells):
+        arrays = self.basis.as_arrays() if hasattr(self.basis, "as_arrays") else self.basis
+        return jk_eri_tiles(self.h, shells, arrays["shell_l"])
+
+    def quartet_count(self, tol=1e-12):
+        return jk_quartet_count(self.h, tol)
+
+    def stats(self):
+        return jk_last_stats(self.h)
+
+    def close(self):
+        if self.h:
+            jk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
