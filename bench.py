@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the AO-direct J/K build on one MI355X.
+
+A step is one jk_build call: the whole hot path (density transform, density
+screen, integral and digestion kernels for every class, back-transform) over
+the 16 Laplace pseudo-densities of the 312-AO medium workload (30 atoms,
+18 heavy 3s2p1d + 12 light 2s1p, 3-primitive contractions, Schwarz 1e-12).
+Densities are resident in HBM before the timed region.  One density's J and
+K is one build, so builds/s = 16 x steps / seconds.
+
+Prints one JSON line.  Per-kernel durations come from HIP events the library
+records around each integral and digestion launch on the build's stream; the
+dominant kernel's algorithmic flops per launch over its mean launch time give
+the roofline entry.  The CPU baseline times the oracle on a strided sample of
+bra shell pairs on the host cores and scales it by the kept-quartet fraction.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "J/K builds/s + ERI quartets/s at 1e-8 rel err, FP64 vs mixed; p50/p99 latency"
+FP64_VALU_PEAK = 78.6      # TFLOP/s, MI355X FP64 vector (256 CU x 64 FMA/clk x 2 x 2.4 GHz)
+CLASS_TAGS = ["0000", "1000", "1010", "1100", "1110", "1111", "2000", "2010", "2011", "2020", "2100",
+              "2110", "2111", "2120", "2121", "2200", "2210", "2211", "2220", "2221", "2222"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2607_05622_amd import synth
+    if name == "tiny":
+        return synth.config0()
+    if name == "medium":
+        return synth.config1()
+    if name == "large":
+        return synth.config2()
+    raise ValueError(name)
+
+
+def cpu_baseline(w, stride):
+    import oracle
+    n_cores = os.cpu_count() or 1
+    oracle.set_threads(n_cores)
+    t0 = time.perf_counter()
+    _, _, done, total = oracle.jk_sample(w.basis, w.D, stride, 0, 1e-12)
+    dt = time.perf_counter() - t0
+    frac = done / max(total, 1)
+    builds_per_s = w.D.shape[0] * frac / dt
+    return {"value": builds_per_s, "unit": "builds/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"bra shell pairs with index % {stride} == 0: {done} of {total} kept quartets "
+                      f"({100 * frac:.2f}%), {dt:.1f} s, scaled by the quartet fraction"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="medium", choices=["tiny", "medium", "large"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-stride", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
+                                   "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2607_05622_amd import jk
+
+    log(f"workload {args.workload}: generating inputs")
+    w = workload(args.workload)
+    dev = torch.device("cuda:0")
+    nd = w.D.shape[0]
+    t0 = time.perf_counter()
+    b = jk.JKBasis(w.basis)
+    setup_s = time.perf_counter() - t0
+    log(f"basis ready: nbf={b.nbf} shells={w.basis.nshells} setup {setup_s:.2f}s")
+    D = torch.tensor(w.D, dtype=torch.float64, device=dev)
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    opts = jk.jk_default_opts()
+    stream = torch.cuda.current_stream(dev)
+    for i in range(args.warmup):
+        jk.jk_build(b.h, D, J, K, opts, stream)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+    jk.jk_profile_enable(b.h, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        jk.jk_build(b.h, D, J, K, opts, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    jk.jk_profile_enable(b.h, False)
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+    st = b.stats()
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+    kernels = []
+    for kind, kname in ((0, "eri_tile"), (1, "digest")):
+        for c in range(21):
+            r = jk.jk_profile_read(b.h, kind, c)
+            if r["launches"] > 0:
+                r.update(kernel=f"{kname}_{CLASS_TAGS[c]}", kind=kname)
+                kernels.append(r)
+    tot_eri_ms = sum(r["ms"] for r in kernels if r["kind"] == "eri_tile")
+    tot_dig_ms = sum(r["ms"] for r in kernels if r["kind"] == "digest")
+    dom = max(kernels, key=lambda r: r["ms"])
+    per_launch_flops = dom["flops"] / dom["launches"]
+    per_launch_ms = dom["ms"] / dom["launches"]
+    achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
+    builds_s = nd * args.steps / (ms * 1e-3)
+    quartets_s = st["quartets"] * args.steps / (ms * 1e-3)
+    eri_tflops = sum(r["flops"] for r in kernels if r["kind"] == "eri_tile") / max(tot_eri_ms, 1e-9) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": builds_s,
+        "unit": "builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.basis.natoms} atoms, {b.nbf} AO ({w.basis.ncart()} Cartesian), "
+                               f"{nd} non-symmetric Laplace pseudo-densities, FP64 path, Schwarz 1e-12",
+                   "nbf": b.nbf, "nd": nd, "precision": args.precision},
+        "quartets_per_s": quartets_s,
+        "function_quartets_per_s": st["function_quartets"] * args.steps / (ms * 1e-3),
+        "primitive_quartets_per_s": st["primitive_quartets"] * args.steps / (ms * 1e-3),
+        "quartets_per_build_call": st["quartets"],
+        "eri_kernels_ms_per_step": tot_eri_ms / args.steps,
+        "digest_kernels_ms_per_step": tot_dig_ms / args.steps,
+        "eri_kernels_tflops": eri_tflops,
+        "eri_kernels_frac_fp64_peak": eri_tflops / FP64_VALU_PEAK,
+        "basis_setup_s": setup_s,
+        "roofline": {
+            "kernel": dom["kernel"],
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VALU_PEAK,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK,
+            "traffic": None,
+            "launches": int(dom["launches"]),
+            "mean_launch_ms": per_launch_ms,
+            "flops_per_launch": per_launch_flops,
+        },
+        "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / args.steps, 4)
+                               for r in sorted(kernels, key=lambda r: -r["ms"])},
+    }
+    b.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a strided sample")
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

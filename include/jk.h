@@ -123,9 +123,10 @@ const char* jk_last_error(void);
 int64_t jk_quartet_count(jk_basis_t h, double tol);
 
 /* Statistics of the most recent jk_build on this handle (host values):
- * out[0] quartets evaluated (after density screening), out[1] of them in
- * FP32, out[2] Cartesian function quartets, out[3] primitive quartets,
- * out[4] algorithmic ERI flops, out[5] algorithmic digestion flops. */
+ * out[0] shell quartets in the Schwarz-screened lists (the density part of
+ * the screen may skip more at run time), out[1] of them in FP32, out[2]
+ * Cartesian function quartets, out[3] primitive quartets, out[4] algorithmic
+ * ERI flops, out[5] algorithmic digestion flops. */
 int jk_last_stats(jk_basis_t h, double out[6]);
 
 /* Contracted, normalized Cartesian ERI tiles (ab|cd) for nq shell quartets
@@ -133,6 +134,17 @@ int jk_last_stats(jk_basis_t h, double out[6]);
  * (host) receives the tiles back to back, each [na][nb][nc][nd] in Cartesian
  * component order.  For tests of the integral kernels.  Synchronous. */
 int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
+
+/* Kernel timing for measurement.  jk_profile_enable(h, 1) makes every later
+ * jk_build on h record a HIP event pair around each integral and digestion
+ * launch, on the build's stream; jk_profile_read synchronizes those events
+ * and returns, per kernel, totals since the last read, then clears them.
+ * kind 0 = integral (ERI tile) kernel, 1 = digestion kernel; cls = canonical
+ * class index 0..20.  out[0] total milliseconds, out[1] launches,
+ * out[2] algorithmic flops, out[3] shell quartets, out[4] bytes written
+ * (integral tiles) or read (tiles, digestion).  Not for concurrent builds. */
+int jk_profile_enable(jk_basis_t h, int32_t on);
+int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]);
 
 #ifdef __cplusplus
 }

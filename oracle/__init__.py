@@ -162,6 +162,22 @@ def jk(basis, D, tol: float = 1e-12):
     return J, K
 
 
+def jk_sample(basis, D, stride: int, offset: int = 0, tol: float = 1e-12):
+    """Partial screened build over bra pairs with index % stride == offset.
+    Returns (J_part, K_part, kept quartets visited, kept quartets total)."""
+    args, _k = _basis_args(basis)
+    n = nbf(basis)
+    D = _dens(D, n)
+    J = np.zeros_like(D)
+    K = np.zeros_like(D)
+    done = ctypes.c_longlong()
+    total = ctypes.c_longlong()
+    _check(_load().oracle_jk_screened_sample(*args, D.shape[0], _dp(D), _dp(J), _dp(K), ctypes.c_double(tol),
+                                             int(stride), int(offset), ctypes.byref(done), ctypes.byref(total)),
+           "jk_screened_sample")
+    return J, K, int(done.value), int(total.value)
+
+
 def count_quartets(basis, D, tol: float = 1e-12) -> int:
     args, _k = _basis_args(basis)
     n = nbf(basis)

@@ -696,8 +696,26 @@ long long oracle_count_quartets(BASIS_ARGS, int nd, const double* D, double tol)
 }
 
 /* Screened build over canonical shell quartets; every *distinct* index
- * permutation of a kept quartet is scattered exactly once. */
+ * permutation of a kept quartet is scattered exactly once.  Only bra pairs
+ * with index % stride == offset are visited (stride 1: the whole build);
+ * *done receives the number of kept quartets visited, *total the number
+ * kept over all bra pairs. */
+static int jk_screened_strided(BASIS_ARGS, int nd, const double* D, double* J, double* K, double tol,
+                               int stride, int offset, long long* done, long long* total);
+
 int oracle_jk_screened(BASIS_ARGS, int nd, const double* D, double* J, double* K, double tol) {
+    return jk_screened_strided(BASIS_PASS, nd, D, J, K, tol, 1, 0, NULL, NULL);
+}
+
+/* A bounded sample of the screened build (for timing the CPU baseline). */
+int oracle_jk_screened_sample(BASIS_ARGS, int nd, const double* D, double* J, double* K, double tol,
+                              int stride, int offset, long long* done, long long* total) {
+    if (stride < 1 || offset < 0 || offset >= stride) return -1;
+    return jk_screened_strided(BASIS_PASS, nd, D, J, K, tol, stride, offset, done, total);
+}
+
+static int jk_screened_strided(BASIS_ARGS, int nd, const double* D, double* J, double* K, double tol,
+                               int stride, int offset, long long* done, long long* total) {
     or_basis b;
     if (make_basis(&b, BASIS_PASS)) return -1;
     int ns = b.nshell;
@@ -713,17 +731,25 @@ int oracle_jk_screened(BASIS_ARGS, int nd, const double* D, double* J, double* K
     int* pb = (int*)malloc(sizeof(int) * (npair + 1));
     for (int a = 0, k = 0; a < ns; a++)
         for (int bb = 0; bb <= a; bb++, k++) { pa[k] = a; pb[k] = bb; }
-#pragma omp parallel num_threads(oracle_get_threads())
+    long long n_done = 0, n_total = 0;
+    if (total) {
+        for (int pab = 0; pab < npair; pab++)
+            for (int pcd = 0; pcd <= pab; pcd++)
+                n_total += keep_quartet(ns, Q, M, pa[pab], pb[pab], pa[pcd], pb[pcd], tol);
+    }
+#pragma omp parallel num_threads(oracle_get_threads()) reduction(+ : n_done)
     {
         double* Jt = (double*)calloc(mat, sizeof(double));
         double* Kt = (double*)calloc(mat, sizeof(double));
         double tile[1296];
 #pragma omp for schedule(dynamic)
         for (int pab = 0; pab < npair; pab++) {
+            if (pab % stride != offset) continue;
             int a = pa[pab], bb = pb[pab];
             for (int pcd = 0; pcd <= pab; pcd++) {
                 int c = pa[pcd], d = pb[pcd];
                 if (!keep_quartet(ns, Q, M, a, bb, c, d, tol)) continue;
+                n_done++;
                 const or_shell *A = &b.sh[a], *B = &b.sh[bb], *C = &b.sh[c], *Dd = &b.sh[d];
                 eri_quartet(A, B, C, Dd, tile);
                 int nA = A->ncart, nB = B->ncart, nC = C->ncart, nD = Dd->ncart;
@@ -780,6 +806,8 @@ int oracle_jk_screened(BASIS_ARGS, int nd, const double* D, double* J, double* K
     }
     from_cart(&b, nd, Jc, J);
     from_cart(&b, nd, Kc, K);
+    if (done) *done = n_done;
+    if (total) *total = n_total;
     free(pa);
     free(pb);
     free(Dc);

@@ -130,6 +130,15 @@ struct jk_basis_s {
     ClassList lists[kNumClass];
     std::vector<int2*> retired;
     double stats[6] = {0, 0, 0, 0, 0, 0};
+    // measurement: event pairs around integral / digestion launches
+    struct ProfRec {
+        int kind, cls;
+        hipEvent_t e0, e1;
+        double flops, quartets, bytes;
+    };
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    double prof_acc[2][kNumClass][5] = {};
 
     ~jk_basis_s() {
         int cur = 0;
@@ -144,6 +153,10 @@ struct jk_basis_s {
         (void)hipFree(d_shell_nf);
         for (auto& l : lists) (void)hipFree(l.dev);
         for (auto* p : retired) (void)hipFree(p);
+        for (auto& r : prof) {
+            (void)hipEventDestroy(r.e0);
+            (void)hipEventDestroy(r.e1);
+        }
         (void)hipSetDevice(cur);
     }
 };
@@ -633,8 +646,25 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
             ea.ns = h->ns;
             ea.tol = o->schwarz_tol;
             ea.out = tiles;
+            const double cost_q = L.prim_quartets / static_cast<double>(L.count);
+            hipEvent_t ev[2] = {nullptr, nullptr};
+            if (h->profiling) {
+                for (auto& x : ev)
+                    if (e == hipSuccess) e = hipEventCreate(&x);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+                if (e != hipSuccess) break;
+            }
             e = launch_eri_tile(c, ea, s);
             if (e != hipSuccess) break;
+            if (h->profiling) {
+                e = hipEventRecord(ev[1], s);
+                if (e != hipSuccess) break;
+                std::lock_guard<std::mutex> g(h->mu);
+                h->prof.push_back({0, c, ev[0], ev[1],
+                                   n * (cost_q * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
+                                        kClassCost[c].hrr_flops),
+                                   static_cast<double>(n), static_cast<double>(n) * NF * sizeof(double)});
+            }
             DigestArgs da{};
             da.quartets = L.dev + q0;
             da.nq = n;
@@ -652,6 +682,18 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
             da.want_j = o->want_j;
             da.want_k = o->want_k;
             e = launch_digest(c, da, s);
+            if (h->profiling && e == hipSuccess) {
+                hipEvent_t e2 = nullptr;
+                e = hipEventCreate(&e2);
+                if (e == hipSuccess) e = hipEventRecord(e2, s);
+                if (e == hipSuccess) {
+                    std::lock_guard<std::mutex> g(h->mu);
+                    h->prof.push_back({1, c, ev[1], e2,
+                                       static_cast<double>(n) * NF * nd *
+                                           (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0)),
+                                       static_cast<double>(n), static_cast<double>(n) * NF * sizeof(double)});
+                }
+            }
         }
         nq_tot += L.count;
         nfq += static_cast<double>(L.count) * NF;
@@ -676,6 +718,45 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
         h->stats[5] = dig_flops;
     }
     if (cur != h->device) (void)hipSetDevice(cur);
+    return JK_OK;
+}
+
+int jk_profile_enable(jk_basis_t h, int32_t on) {
+    if (!h || (on != 0 && on != 1)) return fail(JK_EINVAL, "jk_profile_enable: bad arguments");
+    std::lock_guard<std::mutex> g(h->mu);
+    h->profiling = on != 0;
+    return JK_OK;
+}
+
+int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]) {
+    if (!h || !out || kind < 0 || kind > 1 || cls < 0 || cls >= kNumClass)
+        return fail(JK_EINVAL, "jk_profile_read: bad arguments");
+    std::lock_guard<std::mutex> g(h->mu);
+    // fold every pending record into the accumulators; the start event of a
+    // digestion record is the end event of its integral record, so events
+    // are destroyed only once both uses are folded
+    std::vector<hipEvent_t> dead;
+    for (auto& r : h->prof) {
+        HIPC(hipEventSynchronize(r.e1));
+        float ms = 0.0f;
+        HIPC(hipEventElapsedTime(&ms, r.e0, r.e1));
+        double* a = h->prof_acc[r.kind][r.cls];
+        a[0] += ms;
+        a[1] += 1;
+        a[2] += r.flops;
+        a[3] += r.quartets;
+        a[4] += r.bytes;
+        dead.push_back(r.e0);
+        dead.push_back(r.e1);
+    }
+    h->prof.clear();
+    std::sort(dead.begin(), dead.end());
+    dead.erase(std::unique(dead.begin(), dead.end()), dead.end());
+    for (auto ev : dead) (void)hipEventDestroy(ev);
+    for (int i = 0; i < 5; ++i) {
+        out[i] = h->prof_acc[kind][cls][i];
+        h->prof_acc[kind][cls][i] = 0.0;
+    }
     return JK_OK;
 }
 

@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
     lib.jk_eri_tiles.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     lib.jk_eri_tiles.restype = c_int
+    lib.jk_profile_enable.argtypes = [vp, ctypes.c_int32]
+    lib.jk_profile_enable.restype = c_int
+    lib.jk_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.jk_profile_read.restype = c_int
     _lib = lib
     return lib
 
@@ -194,6 +198,16 @@ def jk_build(h, D, J=None, K=None, opts: jk_build_opts | None = None, stream=Non
     kp = _dev_ptr(K, n, "K") if o.want_k else None
     _check(load().jk_build(h, nd, dp, jp, kp, ctypes.byref(o)))
     return J, K
+
+
+def jk_profile_enable(h, on: bool) -> None:
+    _check(load().jk_profile_enable(h, 1 if on else 0))
+
+
+def jk_profile_read(h, kind: int, cls: int) -> dict:
+    out = (ctypes.c_double * 5)()
+    _check(load().jk_profile_read(h, kind, cls, out))
+    return dict(zip(["ms", "launches", "flops", "quartets", "bytes"], list(out)))
 
 
 def jk_eri_tiles(h, shells, shell_l) -> list:
