@@ -20,10 +20,18 @@ namespace jk {
         return hipGetLastError();                                                                 \
     }                                                                                             \
     hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s) {               \
-        const int per = 256 / a.dg;                                                               \
-        const unsigned g = static_cast<unsigned>((a.nq + per - 1) / per);                         \
-        hipLaunchKernelGGL((k_digest<la, lb, lc, ld>), dim3(g), dim3(256), 0, s, a);              \
+        constexpr int NA = (la + 1) * (la + 2) / 2, NB = (lb + 1) * (lb + 2) / 2;                  \
+        const int W = a.colAw + a.colBw;                                                          \
+        const size_t lds = sizeof(double) * ((a.want_k ? 2 * (NA + NB) * a.G * W : 0) +           \
+                                             (a.want_j ? NA * NB * a.G : 0));                     \
+        const unsigned g = static_cast<unsigned>(8 * ((a.nseg + 7) / 8) * a.ngroups);             \
+        hipLaunchKernelGGL((k_digest<la, lb, lc, ld>), dim3(g), dim3(256), lds, s, a);            \
         return hipGetLastError();                                                                 \
+    }                                                                                             \
+    hipError_t JK_PASTE(digest_prepare_c, idx)(size_t lds_bytes) {                                \
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld>),       \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,                    \
+                                   static_cast<int>(lds_bytes));                                  \
     }
 
 #define JK_SELECT(idx, tag, la, lb, lc, ld) JK_SELECT_##idx(idx, tag, la, lb, lc, ld)

@@ -156,152 +156,216 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
 
 // -------------------------------------------------------------- digest ---
 
-// Lane (slot, x): slot picks the quartet, x the density (strided by dg).
-// Tile element (i j | k l) of quartet q sits at tiles[f * nq + q],
-// f = ((i NB + j) NC + k) ND + l.  Densities and accumulators are
-// [row][col][x] with x innermost (ndp entries per matrix element).
+// One workgroup per (segment, density group).  A segment is a run of
+// quartets of one class sharing the bra pair (a b); its contributions to K
+// fall in four strips -- rows of a and b (K_ac, K_ad, K_bc, K_bd) and columns
+// of a and b (K_ca, K_da, K_cb, K_db) -- restricted to the function windows of
+// the ket shells' angular momenta.  The strips accumulate in LDS and are
+// flushed once with coalesced FP64 atomics: rows into K [x][i][j], columns
+// into KT [x][i][j] (K_{row,col} gets KT[col][row]).  J_ab is reduced over
+// the segment in registers and LDS; J_cd goes straight to J [i][j][x],
+// coalesced over the density lanes.  Scatter of every distinct index
+// permutation with the canonical-fold multiplicity w (Sect. 3, Eq.
+// (quartet_scatter)).
+//
+// Thread t handles density x0 + (t % G) for quartets slot, slot + S, ...
+// (S = blockDim / G); lanes that share a quartet read the same tile words.
+// Digestion of one quartet for one density; OUTER is the unroll pragma of
+// the loops over output elements (full unroll keeps a register tile in
+// registers, no unroll keeps large tiles streaming from memory).
+#define JK_DIGEST_QUARTET(OUTER) \
+            if (a.want_j) { \
+                /* J_ab += w sum_kl I (D_kl + D_lk); J_cd += w sum_ij I (D_ij + D_ji) */ \
+OUTER \
+                for (int k = 0; k < NC; ++k) \
+OUTER \
+                    for (int l = 0; l < ND; ++l) { \
+                        const double s2 = w * (Dv(fc + k, fd + l) + Dv(fd + l, fc + k)); \
+                        double t = 0.0; \
+_Pragma("unroll") \
+                        for (int i = 0; i < NA; ++i) \
+_Pragma("unroll") \
+                            for (int j = 0; j < NB; ++j) { \
+                                const double v = I(i, j, k, l); \
+                                jacc[i * NB + j] = fma(v, s2, jacc[i * NB + j]); \
+                                t = fma(v, Dv(fa + i, fb + j) + Dv(fb + j, fa + i), t); \
+                            } \
+                        unsafeAtomicAdd(Jm + ((fc + k) * nc + fd + l) * ndp, w * t); \
+                    } \
+            } \
+            if (a.want_k) { \
+                /* rows of a: K_ac[i][k] += sum_jl I D_bd[j][l]; K_ad[i][l] += sum_jk I D_bc[j][k] */ \
+                /* cols of a: K_ca[k][i] += sum_jl I D_db[l][j]; K_da[l][i] += sum_jk I D_cb[k][j] */ \
+OUTER \
+                for (int i = 0; i < NA; ++i) { \
+OUTER \
+                    for (int k = 0; k < NC; ++k) { \
+                        double s1 = 0.0, s2 = 0.0; \
+_Pragma("unroll") \
+                        for (int j = 0; j < NB; ++j) \
+_Pragma("unroll") \
+                            for (int l = 0; l < ND; ++l) { \
+                                const double v = I(i, j, k, l); \
+                                s1 = fma(v, Dv(fb + j, fd + l), s1); \
+                                s2 = fma(v, Dv(fd + l, fb + j), s2); \
+                            } \
+                        atomicAdd(S(i, cc + k), w * s1); \
+                        atomicAdd(S(NA + NB + i, cc + k), w * s2); \
+                    } \
+OUTER \
+                    for (int l = 0; l < ND; ++l) { \
+                        double s1 = 0.0, s2 = 0.0; \
+_Pragma("unroll") \
+                        for (int j = 0; j < NB; ++j) \
+_Pragma("unroll") \
+                            for (int k = 0; k < NC; ++k) { \
+                                const double v = I(i, j, k, l); \
+                                s1 = fma(v, Dv(fb + j, fc + k), s1); \
+                                s2 = fma(v, Dv(fc + k, fb + j), s2); \
+                            } \
+                        atomicAdd(S(i, cd + l), w * s1); \
+                        atomicAdd(S(NA + NB + i, cd + l), w * s2); \
+                    } \
+                } \
+                /* rows of b: K_bc[j][k] += sum_il I D_ad[i][l]; K_bd[j][l] += sum_ik I D_ac[i][k] */ \
+                /* cols of b: K_cb[k][j] += sum_il I D_da[l][i]; K_db[l][j] += sum_ik I D_ca[k][i] */ \
+OUTER \
+                for (int j = 0; j < NB; ++j) { \
+OUTER \
+                    for (int k = 0; k < NC; ++k) { \
+                        double s1 = 0.0, s2 = 0.0; \
+_Pragma("unroll") \
+                        for (int i = 0; i < NA; ++i) \
+_Pragma("unroll") \
+                            for (int l = 0; l < ND; ++l) { \
+                                const double v = I(i, j, k, l); \
+                                s1 = fma(v, Dv(fa + i, fd + l), s1); \
+                                s2 = fma(v, Dv(fd + l, fa + i), s2); \
+                            } \
+                        atomicAdd(S(NA + j, cc + k), w * s1); \
+                        atomicAdd(S(2 * NA + NB + j, cc + k), w * s2); \
+                    } \
+OUTER \
+                    for (int l = 0; l < ND; ++l) { \
+                        double s1 = 0.0, s2 = 0.0; \
+_Pragma("unroll") \
+                        for (int i = 0; i < NA; ++i) \
+_Pragma("unroll") \
+                            for (int k = 0; k < NC; ++k) { \
+                                const double v = I(i, j, k, l); \
+                                s1 = fma(v, Dv(fa + i, fc + k), s1); \
+                                s2 = fma(v, Dv(fc + k, fa + i), s2); \
+                            } \
+                        atomicAdd(S(NA + j, cd + l), w * s1); \
+                        atomicAdd(S(2 * NA + NB + j, cd + l), w * s2); \
+                    } \
+                } \
+            } \
+        
+
 template <int LA, int LB, int LC, int LD>
 __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
+    extern __shared__ double lds[];
     constexpr int NA = (LA + 1) * (LA + 2) / 2, NB = (LB + 1) * (LB + 2) / 2;
     constexpr int NC = (LC + 1) * (LC + 2) / 2, ND = (LD + 1) * (LD + 2) / 2;
     constexpr int NF = NA * NB * NC * ND;
-    constexpr bool kRegTile = NF <= 108;
-    const int dg = a.dg;
-    const int slot = threadIdx.x / dg;
-    const int x0 = threadIdx.x - slot * dg;
-    const long long q = static_cast<long long>(blockIdx.x) * (blockDim.x / dg) + slot;
-    if (q >= a.nq || x0 >= a.ndp) return;
-    const int2 bk = a.quartets[q];
-    const PairInfo& P = a.pairs[bk.x];
-    const PairInfo& Q = a.pairs[bk.y];
-    if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) return;
-    double w = 1.0;
-    if (P.sa == P.sb) w *= 0.5;
-    if (Q.sa == Q.sb) w *= 0.5;
-    if (bk.x == bk.y) w *= 0.5;
-    const long long nq = a.nq;
-    const double* __restrict__ tg = a.tiles + q;
-    double treg[kRegTile ? NF : 1];
-    if constexpr (kRegTile) {
+    constexpr int R = 2 * (NA + NB);
+    constexpr bool kRegTile = NF <= 36;
+    const int G = a.G;
+    // blocks of one segment share an XCD (block b runs on XCD b % 8)
+    const int b = blockIdx.x;
+    const int xcd = b & 7, kk = b >> 3;
+    const int seg = (kk / a.ngroups) * 8 + xcd;
+    const int grp = kk - (kk / a.ngroups) * a.ngroups;
+    if (seg >= a.nseg) return;
+    const int x0 = grp * G;
+    const int gn = min(G, a.nd - x0);
+    const int W = a.colAw + a.colBw;
+    const int nstrip = a.want_k ? R * G * W : 0;
+    double* __restrict__ strips = lds;            // [R][G][W]
+    double* __restrict__ jab = lds + nstrip;      // [NA*NB][G]
+    const int nlds = nstrip + (a.want_j ? NA * NB * G : 0);
+    for (int i = threadIdx.x; i < nlds; i += blockDim.x) lds[i] = 0.0;
+    __syncthreads();
+
+    const int2 sg = a.segs[seg];
+    const long long q0 = sg.x - a.qbase;
+    const int slots = blockDim.x / G;
+    const int slot = threadIdx.x / G, g = threadIdx.x - slot * G;
+    const bool active = slot < slots && g < gn;
+    const PairInfo& P = a.pairs[a.quartets[q0].x];
+    const int fa = P.fa, fb = P.fb;
+    const long long nc = a.nc, ndp = a.ndp, nq = a.nq;
+    auto lcol = [&](int col) { return (col >= a.colA0 && col < a.colA0 + a.colAw) ? col - a.colA0 : a.colAw + (col - a.colB0); };
+    double jacc[NA * NB];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) treg[f] = tg[f * nq];
-    }
-    auto I = [&](int i, int j, int k, int l) -> double {
-        const int f = ((i * NB + j) * NC + k) * ND + l;
-        if constexpr (kRegTile) return treg[f];
-        else return tg[static_cast<long long>(f) * nq];
-    };
-    const int fa = P.fa, fb = P.fb, fc = Q.fa, fd = Q.fb;
-    const long long nc = a.nc, ndp = a.ndp;
-    for (int x = x0; x < a.ndp; x += dg) {
+    for (int e = 0; e < NA * NB; ++e) jacc[e] = 0.0;
+    if (active) {
+        const int x = x0 + g;
         const double* __restrict__ Dm = a.D + x;
         auto Dv = [&](int r, int c) -> double { return Dm[(r * nc + c) * ndp]; };
         double* __restrict__ Jm = a.J + x;
-        double* __restrict__ Km = a.K + x;
+        double* __restrict__ sA = strips + static_cast<long long>(g) * W;   // row block 0, density g
+        auto S = [&](int row, int col) -> double* { return sA + static_cast<long long>(row) * G * W + col; };
+#pragma unroll 1
+        for (int qi = slot; qi < sg.y; qi += slots) {
+            const long long q = q0 + qi;
+            const int2 bk = a.quartets[q];
+            const PairInfo& Q = a.pairs[bk.y];
+            if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) continue;
+            double w = 1.0;
+            if (P.sa == P.sb) w *= 0.5;
+            if (Q.sa == Q.sb) w *= 0.5;
+            if (bk.x == bk.y) w *= 0.5;
+            const double* __restrict__ tg = a.tiles + q;
+            double treg[kRegTile ? NF : 1];
+            if constexpr (kRegTile) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) treg[f] = tg[f * nq];
+            }
+            auto I = [&](int i, int j, int k, int l) -> double {
+                const int f = ((i * NB + j) * NC + k) * ND + l;
+                if constexpr (kRegTile) return treg[f];
+                else return tg[static_cast<long long>(f) * nq];
+            };
+            const int fc = Q.fa, fd = Q.fb;
+            const int cc = lcol(fc), cd = lcol(fd);
+            if constexpr (kRegTile) {
+                JK_DIGEST_QUARTET(_Pragma("unroll"))
+            } else {
+                JK_DIGEST_QUARTET(_Pragma("unroll 1"))
+            }
+}
         if (a.want_j) {
-            // J_ab += sum_kl (ij|kl) (D_kl + D_lk), J_cd += sum_ij (ij|kl) (D_ij + D_ji)
-            double s2cd[NC * ND];
 #pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) s2cd[k * ND + l] = Dv(fc + k, fd + l) + Dv(fd + l, fc + k);
-            double s2ab[NA * NB];
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s2ab[i * NB + j] = Dv(fa + i, fb + j) + Dv(fb + j, fa + i);
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int k = 0; k < NC; ++k)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) s = fma(I(i, j, k, l), s2cd[k * ND + l], s);
-                    unsafeAtomicAdd(Jm + ((fa + i) * nc + fb + j) * ndp, w * s);
-                }
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) s = fma(I(i, j, k, l), s2ab[i * NB + j], s);
-                    unsafeAtomicAdd(Jm + ((fc + k) * nc + fd + l) * ndp, w * s);
-                }
+            for (int e = 0; e < NA * NB; ++e) atomicAdd(jab + e * G + g, jacc[e]);
         }
-        if (a.want_k) {
-            // K_ac[i][k] += sum_jl I D_bd[j][l];  K_ca[k][i] += sum_jl I D_db[l][j]
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) {
-                            const double v = I(i, j, k, l);
-                            s1 = fma(v, Dv(fb + j, fd + l), s1);
-                            s2 = fma(v, Dv(fd + l, fb + j), s2);
-                        }
-                    unsafeAtomicAdd(Km + ((fa + i) * nc + fc + k) * ndp, w * s1);
-                    unsafeAtomicAdd(Km + ((fc + k) * nc + fa + i) * ndp, w * s2);
-                }
-            // K_bc[j][k] += sum_il I D_ad[i][l];  K_cb[k][j] += sum_il I D_da[l][i]
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) {
-                            const double v = I(i, j, k, l);
-                            s1 = fma(v, Dv(fa + i, fd + l), s1);
-                            s2 = fma(v, Dv(fd + l, fa + i), s2);
-                        }
-                    unsafeAtomicAdd(Km + ((fb + j) * nc + fc + k) * ndp, w * s1);
-                    unsafeAtomicAdd(Km + ((fc + k) * nc + fb + j) * ndp, w * s2);
-                }
-            // K_ad[i][l] += sum_jk I D_bc[j][k];  K_da[l][i] += sum_jk I D_cb[k][j]
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-#pragma unroll
-                        for (int k = 0; k < NC; ++k) {
-                            const double v = I(i, j, k, l);
-                            s1 = fma(v, Dv(fb + j, fc + k), s1);
-                            s2 = fma(v, Dv(fc + k, fb + j), s2);
-                        }
-                    unsafeAtomicAdd(Km + ((fa + i) * nc + fd + l) * ndp, w * s1);
-                    unsafeAtomicAdd(Km + ((fd + l) * nc + fa + i) * ndp, w * s2);
-                }
-            // K_bd[j][l] += sum_ik I D_ac[i][k];  K_db[l][j] += sum_ik I D_ca[k][i]
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int k = 0; k < NC; ++k) {
-                            const double v = I(i, j, k, l);
-                            s1 = fma(v, Dv(fa + i, fc + k), s1);
-                            s2 = fma(v, Dv(fc + k, fa + i), s2);
-                        }
-                    unsafeAtomicAdd(Km + ((fb + j) * nc + fd + l) * ndp, w * s1);
-                    unsafeAtomicAdd(Km + ((fd + l) * nc + fb + j) * ndp, w * s2);
-                }
+    }
+    __syncthreads();
+    // flush: column index fastest, so lanes write consecutive addresses
+    if (a.want_k) {
+        const long long mat = nc * nc;
+        for (int idx = threadIdx.x; idx < R * G * W; idx += blockDim.x) {
+            const int c = idx % W;
+            const int rg = idx / W;
+            const int gg = rg % G, r = rg / G;
+            if (gg >= gn) continue;
+            const double v = strips[idx];
+            if (v == 0.0) continue;
+            const int col = c < a.colAw ? a.colA0 + c : a.colB0 + (c - a.colAw);
+            const long long x = x0 + gg;
+            if (r < NA) unsafeAtomicAdd(a.K + x * mat + (fa + r) * nc + col, v);
+            else if (r < NA + NB) unsafeAtomicAdd(a.K + x * mat + (fb + r - NA) * nc + col, v);
+            else if (r < 2 * NA + NB) unsafeAtomicAdd(a.KT + x * mat + (fa + r - NA - NB) * nc + col, v);
+            else unsafeAtomicAdd(a.KT + x * mat + (fb + r - 2 * NA - NB) * nc + col, v);
+        }
+    }
+    if (a.want_j) {
+        for (int idx = threadIdx.x; idx < NA * NB * G; idx += blockDim.x) {
+            const int e = idx / G, gg = idx - e * G;
+            if (gg >= gn) continue;
+            const int i = e / NB, j = e - i * NB;
+            unsafeAtomicAdd(a.J + ((fa + i) * nc + fb + j) * ndp + x0 + gg, jab[idx]);
         }
     }
 }

@@ -95,11 +95,25 @@ const double kSphD[5][6] = {
 
 int class_nf(int cls) { return kClassCost[cls].nfunc; }
 
+// Runs of quartets sharing a bra pair, capped in length: the unit of work of
+// the digestion kernel.
+constexpr int kSegMax = 1024;
+
+struct Chunk {
+    int s0, s1;          // segments [s0, s1)
+    long long q0, q1;    // quartets [q0, q1) of the class list
+};
+
 struct ClassList {
     long long count = 0;
     double prim_quartets = 0;   // sum of nprim_bra * nprim_ket
     int2* dev = nullptr;
+    std::vector<int2> segs;     // (first quartet, count)
+    int2* dev_segs = nullptr;
 };
+
+// pair class X -> (la, lb)
+const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
 
 }  // namespace
 
@@ -129,6 +143,9 @@ struct jk_basis_s {
     double list_tol = -1.0;
     ClassList lists[kNumClass];
     std::vector<int2*> retired;
+    int lds_cap = 65536;               // dynamic LDS bytes per workgroup
+    int lw_off[kMaxL + 1] = {}, lw_len[kMaxL + 1] = {};   // Cartesian function window per l
+    size_t prepared[kNumClass] = {};   // LDS attribute already granted per class
     double stats[6] = {0, 0, 0, 0, 0, 0};
     // measurement: event pairs around integral / digestion launches
     struct ProfRec {
@@ -151,7 +168,10 @@ struct jk_basis_s {
         (void)hipFree(d_umap);
         (void)hipFree(d_shell_f0);
         (void)hipFree(d_shell_nf);
-        for (auto& l : lists) (void)hipFree(l.dev);
+        for (auto& l : lists) {
+            (void)hipFree(l.dev);
+            (void)hipFree(l.dev_segs);
+        }
         for (auto* p : retired) (void)hipFree(p);
         for (auto& r : prof) {
             (void)hipEventDestroy(r.e0);
@@ -274,10 +294,22 @@ int build_lists(jk_basis_s* h, double tol) {
             }
             fresh[cls].count = static_cast<long long>(out.size());
             fresh[cls].prim_quartets = primq;
+            // segments: bra-pair runs of at most kSegMax quartets
+            auto& segs = fresh[cls].segs;
+            for (size_t q = 0; q < out.size();) {
+                size_t e = q + 1;
+                while (e < out.size() && out[e].x == out[q].x && static_cast<int>(e - q) < kSegMax) ++e;
+                segs.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
+                q = e;
+            }
             if (!out.empty()) {
                 int rc = upload(&fresh[cls].dev, out);
+                if (!rc) rc = upload(&fresh[cls].dev_segs, segs);
                 if (rc) {
-                    for (auto& f : fresh) (void)hipFree(f.dev);
+                    for (auto& f : fresh) {
+                        (void)hipFree(f.dev);
+                        (void)hipFree(f.dev_segs);
+                    }
                     return rc;
                 }
             }
@@ -285,6 +317,7 @@ int build_lists(jk_basis_s* h, double tol) {
     }
     for (int c = 0; c < kNumClass; ++c) {
         if (h->lists[c].dev) h->retired.push_back(h->lists[c].dev);
+        if (h->lists[c].dev_segs) h->retired.push_back(h->lists[c].dev_segs);
         h->lists[c] = fresh[c];
     }
     h->list_tol = tol;
@@ -297,22 +330,16 @@ int ensure_lists(jk_basis_s* h, double tol) {
     return build_lists(h, tol);
 }
 
-int choose_dg(int nd) {
-    int dg = 16;
-    while (dg > 1 && ((nd + dg - 1) / dg) * dg - nd > nd / 8) dg /= 2;
-    return dg;
-}
-
 struct Plan {
     int ndp, dg;
-    size_t off_D, off_J, off_K, off_dmax, off_tile, total;
+    size_t off_D, off_J, off_K, off_KT, off_dmax, off_tile, total;
     long long tile_elems;
 };
 
 Plan make_plan(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     Plan p{};
-    p.dg = choose_dg(nd);
-    p.ndp = ((nd + p.dg - 1) / p.dg) * p.dg;
+    p.dg = 1;
+    p.ndp = nd;
     const size_t mat = static_cast<size_t>(h->nc) * h->nc * p.ndp * sizeof(double);
     auto al = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
     size_t off = 0;
@@ -320,8 +347,11 @@ Plan make_plan(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     off += al(mat);
     p.off_J = off;
     if (o->want_j) off += al(mat);
+    const size_t kmat = static_cast<size_t>(h->nc) * h->nc * nd * sizeof(double);
     p.off_K = off;
-    if (o->want_k) off += al(mat);
+    if (o->want_k) off += al(kmat);
+    p.off_KT = off;
+    if (o->want_k) off += al(kmat);
     p.off_dmax = off;
     off += al(static_cast<size_t>(h->ns) * h->ns * sizeof(double));
     // tile buffer: the largest class volume, capped
@@ -454,6 +484,20 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     }
     h->f0_int[ns] = fc;
     h->nc = fc;
+    for (int l = kMaxL; l >= 0; --l) {
+        h->lw_off[l] = fc;
+        h->lw_len[l] = 0;
+    }
+    for (int si = ns - 1; si >= 0; --si) {
+        const int l = h->l_int[si];
+        h->lw_off[l] = h->f0_int[si];
+        h->lw_len[l] += ncart(l);
+    }
+    {
+        int cap = 0;
+        HIPC(hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+        h->lds_cap = cap > 0 ? cap : 65536;
+    }
 
     // shell pairs (a >= b internal, la >= lb) and primitive pairs
     h->pair_id.assign(static_cast<size_t>(ns) * ns, -1);
@@ -621,21 +665,60 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     double* Dc = reinterpret_cast<double*>(ws + p.off_D);
     double* Jc = o->want_j ? reinterpret_cast<double*>(ws + p.off_J) : nullptr;
     double* Kc = o->want_k ? reinterpret_cast<double*>(ws + p.off_K) : nullptr;
+    double* KTc = o->want_k ? reinterpret_cast<double*>(ws + p.off_KT) : nullptr;
     double* dmax = reinterpret_cast<double*>(ws + p.off_dmax);
     double* tiles = reinterpret_cast<double*>(ws + p.off_tile);
     const long long mat = static_cast<long long>(h->nc) * h->nc * p.ndp;
+    const long long kmat = static_cast<long long>(h->nc) * h->nc * nd;
     hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, p.ndp, Dc, s);
     if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, p.ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
     if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
-    if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
+    if (e == hipSuccess && Kc) e = launch_zero(Kc, kmat, s);
+    if (e == hipSuccess && KTc) e = launch_zero(KTc, kmat, s);
     double nq_tot = 0, nfq = 0, npq = 0, eri_flops = 0, dig_flops = 0;
     for (int c = 0; c < kNumClass && e == hipSuccess; ++c) {
         const ClassList& L = h->lists[c];
         if (L.count == 0) continue;
         const int NF = class_nf(c);
-        const long long chunk = std::max<long long>(1, p.tile_elems / NF);
-        for (long long q0 = 0; q0 < L.count && e == hipSuccess; q0 += chunk) {
-            const long long n = std::min(chunk, L.count - q0);
+        int X = 0;
+        while (quartet_class(X + 1, 0) <= c && X + 1 < kNumPairClass) ++X;
+        const int Y = c - quartet_class(X, 0);
+        const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
+        const int NA = ncart(la), NB = ncart(lb);
+        // LDS windows: Cartesian functions of the ket shells' angular momenta
+        const int colA0 = h->lw_off[lc], colAw = h->lw_len[lc];
+        const int colB0 = ld != lc ? h->lw_off[ld] : 0, colBw = ld != lc ? h->lw_len[ld] : 0;
+        const size_t per_density = sizeof(double) * ((o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0) +
+                                                     (o->want_j ? NA * NB : 0));
+        int G = 16;
+        while (G > 1 && (G / 2 >= nd || G * per_density > static_cast<size_t>(h->lds_cap))) G /= 2;
+        if (per_density > static_cast<size_t>(h->lds_cap)) {
+            if (own) (void)hipFreeAsync(ws, s);
+            return fail(JK_EUNSUPPORTED, "jk_build: class %d needs %zu bytes of LDS per density (limit %d)", c,
+                        per_density, h->lds_cap);
+        }
+        const size_t lds_bytes = G * per_density;
+        {
+            std::lock_guard<std::mutex> g(h->mu);
+            if (h->prepared[c] < lds_bytes) {
+                e = digest_prepare(c, lds_bytes);
+                if (e == hipSuccess) h->prepared[c] = lds_bytes;
+            }
+        }
+        if (e != hipSuccess) break;
+        const long long cap = p.tile_elems / NF;
+        const int nseg = static_cast<int>(L.segs.size());
+        for (int s0 = 0; s0 < nseg && e == hipSuccess;) {
+            // chunk: whole segments whose quartets fit the tile buffer
+            const long long q0 = L.segs[s0].x;
+            int s1 = s0;
+            while (s1 < nseg && L.segs[s1].x + L.segs[s1].y - q0 <= cap) ++s1;
+            if (s1 == s0) {
+                e = hipErrorInvalidValue;   // a segment larger than the work buffer: never by construction
+                break;
+            }
+            const long long q1 = L.segs[s1 - 1].x + L.segs[s1 - 1].y;
+            const long long n = q1 - q0;
             EriTileArgs ea{};
             ea.quartets = L.dev + q0;
             ea.nq = n;
@@ -668,6 +751,12 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
             DigestArgs da{};
             da.quartets = L.dev + q0;
             da.nq = n;
+            da.segs = L.dev_segs + s0;
+            da.qbase = q0;
+            da.nseg = s1 - s0;
+            da.G = G;
+            da.ngroups = (nd + G - 1) / G;
+            da.nd = nd;
             da.pairs = h->d_pairs;
             da.dmax = dmax;
             da.ns = h->ns;
@@ -676,9 +765,13 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
             da.D = Dc;
             da.J = Jc;
             da.K = Kc;
+            da.KT = KTc;
             da.nc = h->nc;
             da.ndp = p.ndp;
-            da.dg = p.dg;
+            da.colA0 = colA0;
+            da.colAw = colAw;
+            da.colB0 = colB0;
+            da.colBw = colBw;
             da.want_j = o->want_j;
             da.want_k = o->want_k;
             e = launch_digest(c, da, s);
@@ -691,9 +784,11 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
                     h->prof.push_back({1, c, ev[1], e2,
                                        static_cast<double>(n) * NF * nd *
                                            (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0)),
-                                       static_cast<double>(n), static_cast<double>(n) * NF * sizeof(double)});
+                                       static_cast<double>(n),
+                                       static_cast<double>(n) * NF * sizeof(double) * da.ngroups});
                 }
             }
+            s0 = s1;
         }
         nq_tot += L.count;
         nfq += static_cast<double>(L.count) * NF;
@@ -702,7 +797,7 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
                      static_cast<double>(L.count) * kClassCost[c].hrr_flops;
         dig_flops += static_cast<double>(L.count) * NF * nd * (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0));
     }
-    if (e == hipSuccess) e = launch_cart2sph(Jc, Kc, nd, h->nf, h->d_umap, h->nc, p.ndp, J, K, s);
+    if (e == hipSuccess) e = launch_cart2sph(Jc, Kc, KTc, nd, h->nf, h->d_umap, h->nc, p.ndp, J, K, s);
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (e == hipSuccess) e = e2;

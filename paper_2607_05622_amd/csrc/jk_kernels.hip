@@ -40,11 +40,11 @@ __global__ void k_sph2cart(const double* __restrict__ D, int nd, int nf, const C
     }
 }
 
-// J[x][m][n] = sum T[i][m] (Jc[i][j][x] + Jc[j][i][x]) T[j][n], K likewise without
-// the transpose.
-__global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restrict__ Kc, int nd, int nf,
-                           const UserMap* __restrict__ umap, int nc, int ndp, double* __restrict__ J,
-                           double* __restrict__ K) {
+// J[x][m][n] = sum T[i][m] (Jc[i][j][x] + Jc[j][i][x]) T[j][n] with Jc density-innermost;
+// K[x][m][n] = sum T[i][m] (Kc[x][i][j] + KTc[x][j][i]) T[j][n].
+__global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restrict__ Kc,
+                           const double* __restrict__ KTc, int nd, int nf, const UserMap* __restrict__ umap,
+                           int nc, int ndp, double* __restrict__ J, double* __restrict__ K) {
     const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= static_cast<long long>(nf) * nf) return;
     const int m = static_cast<int>(t / nf), n = static_cast<int>(t - static_cast<long long>(m) * nf);
@@ -57,7 +57,9 @@ __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restri
                 const long long ij = (static_cast<long long>(um.idx[u]) * nc + un.idx[v]) * ndp + x;
                 const long long ji = (static_cast<long long>(un.idx[v]) * nc + um.idx[u]) * ndp + x;
                 if (J) sj = fma(c, Jc[ij] + Jc[ji], sj);
-                if (K) sk = fma(c, Kc[ij], sk);
+                const long long kij = (static_cast<long long>(x) * nc + um.idx[u]) * nc + un.idx[v];
+                const long long kji = (static_cast<long long>(x) * nc + un.idx[v]) * nc + um.idx[u];
+                if (K) sk = fma(c, Kc[kij] + KTc[kji], sk);
             }
         if (J) J[static_cast<long long>(x) * nf * nf + t] = sj;
         if (K) K[static_cast<long long>(x) * nf * nf + t] = sk;
@@ -119,11 +121,22 @@ hipError_t launch_sph2cart(const double* D, int nd, int nf, const CartMap* cmap,
     return hipGetLastError();
 }
 
-hipError_t launch_cart2sph(const double* Jc, const double* Kc, int nd, int nf, const UserMap* umap, int nc,
-                           int ndp, double* J, double* K, hipStream_t s) {
+hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc, int nd, int nf,
+                           const UserMap* umap, int nc, int ndp, double* J, double* K, hipStream_t s) {
     const long long n = static_cast<long long>(nf) * nf;
-    hipLaunchKernelGGL(k_cart2sph, dim3(blocks_for(n, 256)), dim3(256), 0, s, Jc, Kc, nd, nf, umap, nc, ndp, J, K);
+    hipLaunchKernelGGL(k_cart2sph, dim3(blocks_for(n, 256)), dim3(256), 0, s, Jc, Kc, KTc, nd, nf, umap, nc, ndp,
+                       J, K);
     return hipGetLastError();
+}
+
+hipError_t digest_prepare(int cls, size_t lds_bytes) {
+    switch (cls) {
+#define JK_CASE(n) \
+    case n: return digest_prepare_c##n(lds_bytes);
+        JK_FOR_CLASS_INDEX(JK_CASE)
+#undef JK_CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,

@@ -37,8 +37,14 @@ struct EriTileArgs {
 };
 
 struct DigestArgs {
-    const int2* quartets;
-    long long nq;
+    const int2* quartets;   // this chunk's quartets
+    long long nq;           // quartets in the chunk (tile stride)
+    const int2* segs;       // this chunk's segments (first quartet in the class list, count)
+    long long qbase;        // class-list index of the chunk's first quartet
+    int nseg;
+    int G;                  // densities per workgroup (power of two)
+    int ngroups;            // ceil(nd / G)
+    int nd;
     const PairInfo* pairs;
     const double* dmax;
     int ns;
@@ -46,17 +52,23 @@ struct DigestArgs {
     const double* tiles;    // [NF][nq]
     const double* D;        // [nc][nc][ndp]
     double* J;              // [nc][nc][ndp]
-    double* K;
-    int nc, ndp, dg;
+    double* K;              // [nd][nc][nc], row-strip contributions
+    double* KT;             // [nd][nc][nc], column-strip contributions, transposed
+    int nc, ndp;
+    int colA0, colAw, colB0, colBw;   // LDS column windows (ket shells' functions)
     int want_j, want_k;
 };
+
+// Allow the digestion kernel of class cls up to lds_bytes of dynamic LDS.
+hipError_t digest_prepare(int cls, size_t lds_bytes);
 
 // one launcher pair per canonical class index, defined in jk_class.hip
 #define JK_FOR_CLASS_INDEX(X) \
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 #define JK_DECLARE(n)                                                       \
     hipError_t launch_eri_tile_c##n(const EriTileArgs& a, hipStream_t s); \
-    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s);
+    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s);    \
+    hipError_t digest_prepare_c##n(size_t lds_bytes);
 JK_FOR_CLASS_INDEX(JK_DECLARE)
 #undef JK_DECLARE
 
@@ -64,8 +76,8 @@ hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s);
 hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s);
 hipError_t launch_sph2cart(const double* D, int nd, int nf, const CartMap* cmap, int nc, int ndp, double* Dc,
                            hipStream_t s);
-hipError_t launch_cart2sph(const double* Jc, const double* Kc, int nd, int nf, const UserMap* umap, int nc,
-                           int ndp, double* J, double* K, hipStream_t s);
+hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc, int nd, int nf,
+                           const UserMap* umap, int nc, int ndp, double* J, double* K, hipStream_t s);
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,
                             int ns, double* dmax, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
