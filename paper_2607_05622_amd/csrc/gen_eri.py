@@ -227,6 +227,102 @@ class Emitter:
         )
 
 
+# Classes with more contracted targets than SPLIT_NACC are evaluated in
+# passes over groups of bra components e (about TARGET_BUDGET accumulators
+# per group), so that no pass keeps more than a few dozen accumulators live:
+# each pass runs the primitive loop over its own recurrence cone, applies
+# HRR-CD to its e's and stores (e0|cd) to scratch; HRR-AB then assembles the
+# tile one ket function pair at a time.
+SPLIT_NACC = 40
+TARGET_BUDGET = 32
+
+
+def split_plan(em, info):
+    """Groups of e (in the sorted e order) and the derived index sets."""
+    leaves = info["leaves"]
+    es = sorted({e for e, f in leaves}, key=lambda e: (sum(e), e))
+    fs = sorted({f for e, f in leaves}, key=lambda f: (sum(f), f))
+    per = max(1, TARGET_BUDGET // len(fs))
+    groups = [es[i:i + per] for i in range(0, len(es), per)]
+    return es, fs, groups
+
+
+def emit_split(em, info, R="R"):
+    """Code for the split evaluation of one class: per-group VRR and HRR-CD,
+    and the HRR-AB applied per ket function pair."""
+    la, lb, lc, ld = em.la, em.lb, em.lc, em.ld
+    es, fs, groups = split_plan(em, info)
+    eidx = {e: i for i, e in enumerate(es)}
+    fidx = {f: i for i, f in enumerate(fs)}
+    cds = [(c, d) for c in cart_lex(lc) for d in cart_lex(ld)]
+    abs_ = [(a, b) for a in cart_lex(la) for b in cart_lex(lb)]
+    X = "xyz"
+    out = {"groups": [], "NE": len(es), "NCD": len(cds), "NAB": len(abs_), "NFT": len(fs)}
+    vrr_flops_total = 0
+    hrr_flops = 0
+    for gi, grp in enumerate(groups):
+        targets = [(e, f, 0) for e in grp for f in fs]
+        code, fl, nn = em.emit_vrr(targets)
+        vrr_flops_total += fl
+        acc_lines = ["acc[%d] += %s;" % (i, em.vname(t)) for i, t in enumerate(targets)]
+        # HRR-CD on this group's e's: (e|c, d+1_i) = (e|c+1_i, d) + CD_i (e|c, d)
+        hc = []
+        memo = {}
+
+        def node(e, c, d):
+            key = (e, c, d)
+            if key in memo:
+                return memo[key]
+            if sum(d) == 0:
+                nm = "acc[%d]" % (grp.index(e) * len(fs) + fidx[c])
+                memo[key] = nm
+                return nm
+            i = pick_dir(d)
+            n1 = node(e, add(c, i), add(d, i, -1))
+            n2 = node(e, c, add(d, i, -1))
+            nm = "u_%d%d%d_%d%d%d_%d%d%d" % (e + c + d)
+            hc.append("const R %s = %s + CD%s * %s;" % (nm, n1, X[i], n2))
+            memo[key] = nm
+            return nm
+        sinks = []
+        for e in grp:
+            for ci, (c, d) in enumerate(cds):
+                nm = node(e, c, d)
+                sinks.append("sink(%d, %s);" % (eidx[e] * len(cds) + ci, nm))
+        hrr_flops += 2 * len(hc)
+        out["groups"].append(dict(n=len(targets), vrr=code, acc=acc_lines, hrrcd=hc, sinks=sinks))
+    # HRR-AB: (a, b+1_i| = (a+1_i, b| + AB_i (a, b|, leaves (e, 0|
+    memo = {}
+    hab = []
+    loads = []
+
+    def nodeab(a, b):
+        key = (a, b)
+        if key in memo:
+            return memo[key]
+        if sum(b) == 0:
+            nm = "w_%d%d%d" % a
+            loads.append("const R %s = load(%d);" % (nm, eidx[a]))
+            memo[key] = nm
+            return nm
+        i = pick_dir(b)
+        n1 = nodeab(add(a, i), add(b, i, -1))
+        n2 = nodeab(a, add(b, i, -1))
+        nm = "v_%d%d%d_%d%d%d" % (a + b)
+        hab.append("const R %s = %s + AB%s * %s;" % (nm, n1, X[i], n2))
+        memo[key] = nm
+        return nm
+    ab_sinks = []
+    for ai, (a, b) in enumerate(abs_):
+        ab_sinks.append("sink(%d, %s);" % (ai, nodeab(a, b)))
+    hrr_flops += 2 * len(hab) * len(cds)
+    out["hab"] = loads + hab
+    out["ab_sinks"] = ab_sinks
+    out["vrr_flops_total"] = vrr_flops_total
+    out["hrr_flops"] = hrr_flops
+    return out
+
+
 # Per-primitive-quartet set-up and Boys cost (flops), counted from the kernel
 # source: the quartet geometry (~34), the prefactor (3), Taylor + exp +
 # downward recursion of the Boys function (2*7 + 2*8 + 3L), folding the
@@ -275,6 +371,51 @@ def emit_all(path, counts_path=None):
             src.append("    acc[%d] += %s;" % (i, v))
         src.append("  }")
         # HRR: acc -> out via a functor sink(index, value)
+        split = info["nacc"] > SPLIT_NACC
+        src.append("  static constexpr bool kSplit = %s;" % ("true" if split else "false"))
+        if split:
+            sp = emit_split(em, info)
+            info["split"] = sp
+            gn = [g["n"] for g in sp["groups"]]
+            src.append("  static constexpr int NE = %d, NCD = %d, NAB = %d, NG = %d, GMAX = %d;" % (
+                sp["NE"], sp["NCD"], sp["NAB"], len(gn), max(gn)))
+            src.append("  template <int G> __device__ static __forceinline__ void vrr_group(const R* __restrict__ F, const VrrCoef<R>& k, R* __restrict__ acc) {")
+            src.append("    const R PAx = k.PA[0], PAy = k.PA[1], PAz = k.PA[2];")
+            src.append("    const R WPx = k.WP[0], WPy = k.WP[1], WPz = k.WP[2];")
+            src.append("    const R QCx = k.QC[0], QCy = k.QC[1], QCz = k.QC[2];")
+            src.append("    const R WQx = k.WQ[0], WQy = k.WQ[1], WQz = k.WQ[2];")
+            src.append("    const R rp = k.rp, rq = k.rq;")
+            src.append("    const R o2p_1 = k.o2p, o2p_2 = R(2) * k.o2p, o2p_3 = R(3) * k.o2p;")
+            src.append("    const R o2q_1 = k.o2q, o2q_2 = R(2) * k.o2q, o2q_3 = R(3) * k.o2q;")
+            src.append("    const R o2pq_1 = k.o2pq, o2pq_2 = R(2) * k.o2pq, o2pq_3 = R(3) * k.o2pq, o2pq_4 = R(4) * k.o2pq;")
+            src.append("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
+            src.append("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz; (void)rp; (void)rq;")
+            src.append("    (void)o2p_1; (void)o2p_2; (void)o2p_3; (void)o2q_1; (void)o2q_2; (void)o2q_3;")
+            src.append("    (void)o2pq_1; (void)o2pq_2; (void)o2pq_3; (void)o2pq_4;")
+            for gi, g in enumerate(sp["groups"]):
+                src.append("    %sif constexpr (G == %d) {" % ("" if gi == 0 else "else ", gi))
+                for line in g["vrr"] + g["acc"]:
+                    src.append("      " + line)
+                src.append("    }")
+            src.append("  }")
+            src.append("  template <int G, class Sink>")
+            src.append("  __device__ static __forceinline__ void hrrcd_group(const R* __restrict__ acc, const R CD[3], Sink&& sink) {")
+            src.append("    const R CDx = CD[0], CDy = CD[1], CDz = CD[2];")
+            src.append("    (void)CDx; (void)CDy; (void)CDz;")
+            for gi, g in enumerate(sp["groups"]):
+                src.append("    %sif constexpr (G == %d) {" % ("" if gi == 0 else "else ", gi))
+                for line in g["hrrcd"] + g["sinks"]:
+                    src.append("      " + line)
+                src.append("    }")
+            src.append("  }")
+            src.append("  template <class Load, class Sink>")
+            src.append("  __device__ static __forceinline__ void hrrab(Load&& load, const R AB[3], Sink&& sink) {")
+            src.append("    const R ABx = AB[0], ABy = AB[1], ABz = AB[2];")
+            src.append("    (void)ABx; (void)ABy; (void)ABz;")
+            for line in sp["hab"] + sp["ab_sinks"]:
+                src.append("    " + line)
+            src.append("  }")
+            src.append("  static constexpr int GN[NG] = {%s};" % ", ".join(str(x) for x in gn))
         src.append("  template <class Sink>")
         src.append("  __device__ static __forceinline__ void hrr(const R* __restrict__ acc, const R AB[3], const R CD[3], Sink&& sink) {")
         src.append("    const R ABx = AB[0], ABy = AB[1], ABz = AB[2];")
@@ -299,10 +440,14 @@ def emit_all(path, counts_path=None):
     counts = {}
     for info in infos:
         L = info["L"]
+        sp = info.get("split")
         counts[class_tag(info["cls"])] = dict(
             L=L, nfunc=info["nfunc"], nacc=info["nacc"], vrr_nodes=info["vrr_nodes"],
             vrr_flops=info["vrr_flops"], hrr_flops=info["hrr_flops"],
-            prim_flops=prim_setup_flops(L, info["nacc"]))
+            prim_flops=prim_setup_flops(L, info["nacc"]),
+            split_groups=len(sp["groups"]) if sp else 1,
+            split_vrr_flops=sp["vrr_flops_total"] if sp else info["vrr_flops"],
+            split_hrr_flops=sp["hrr_flops"] if sp else info["hrr_flops"])
     if counts_path:
         with open(counts_path, "w") as fh:
             json.dump(counts, fh, indent=1, sort_keys=True)

@@ -16,7 +16,10 @@ namespace jk {
     static_assert(idx >= 0, "");                                                                  \
     hipError_t JK_PASTE(launch_eri_tile_c, idx)(const EriTileArgs& a, hipStream_t s) {            \
         const unsigned g = static_cast<unsigned>((a.nq + 255) / 256);                             \
-        hipLaunchKernelGGL(k_eri_tile<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);            \
+        if constexpr (Eri##tag<double>::kSplit)                                                   \
+            hipLaunchKernelGGL(k_eri_tile_split<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);  \
+        else                                                                                      \
+            hipLaunchKernelGGL(k_eri_tile<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);        \
         return hipGetLastError();                                                                 \
     }                                                                                             \
     hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s) {               \

@@ -154,6 +154,62 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
     C::hrr(acc, P.AB, Q.AB, [&](int f, double v) { out[static_cast<long long>(f) * nq] = v; });
 }
 
+// High angular momentum: passes over groups of bra components.  Each pass
+// runs the primitive loop for its own part of the vertical recurrence, keeps
+// only its group's accumulators live, applies HRR-CD and parks (e0|cd) in
+// scratch; HRR-AB then assembles the tile one ket function pair at a time.
+template <class C, int G>
+__device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const PairInfo& P, const PairInfo& Q,
+                                               double* __restrict__ scr, long long nq) {
+    if constexpr (G < C::NG) {
+        double acc[C::GMAX];
+#pragma unroll
+        for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
+        const PrimPair* __restrict__ pb = a.prims + P.prim_off;
+        const PrimPair* __restrict__ pk = a.prims + Q.prim_off;
+        const int nb = P.nprim, nk = Q.nprim;
+#pragma unroll 1
+        for (int i = 0; i < nb; ++i) {
+            const PrimPair pp = pb[i];
+#pragma unroll 1
+            for (int j = 0; j < nk; ++j) {
+                const PrimPair qq = pk[j];
+                VrrCoef<double> k;
+                double T, pref;
+                prim_setup(pp, qq, P.A, Q.A, k, T, pref);
+                double F[C::L + 1];
+                boys_f64<C::L>(T, pref, a.boys, F);
+                C::template vrr_group<G>(F, k, acc);
+            }
+        }
+        C::template hrrcd_group<G>(acc, Q.AB, [&](int idx, double v) { scr[static_cast<long long>(idx) * nq] = v; });
+        eri_split_pass<C, G + 1>(a, P, Q, scr, nq);
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_eri_tile_split(EriTileArgs a) {
+    const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.nq) return;
+    const int2 bk = a.quartets[q];
+    const PairInfo& P = a.pairs[bk.x];
+    const PairInfo& Q = a.pairs[bk.y];
+    double* __restrict__ out = a.out + q;
+    const long long nq = a.nq;
+    if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) {
+#pragma unroll 1
+        for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = 0.0;
+        return;
+    }
+    double* __restrict__ scr = a.scratch + q;
+    eri_split_pass<C, 0>(a, P, Q, scr, nq);
+#pragma unroll 1
+    for (int cd = 0; cd < C::NCD; ++cd) {
+        C::hrrab([&](int e) -> double { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, P.AB,
+                 [&](int ab, double v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = v; });
+    }
+}
+
 // -------------------------------------------------------------- digest ---
 
 // One workgroup per (segment, density group).  A segment is a run of

@@ -200,8 +200,10 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
     if (nq == 0) return JK_OK;
     int2* dq = nullptr;
     double* dout = nullptr;
+    double* dscr = nullptr;
     HIPC(hipMalloc(&dq, nq * sizeof(int2)));
     HIPC(hipMalloc(&dout, nq * NF * sizeof(double)));
+    HIPC(hipMalloc(&dscr, nq * NF * sizeof(double)));
     int rc = JK_OK;
     do {
         if (hipMemcpy(dq, quartets.data(), nq * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
@@ -218,6 +220,7 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
         a.ns = h->ns;
         a.tol = 0.0;
         a.out = dout;
+        a.scratch = dscr;
         hipError_t e = launch_eri_tile(cls, a, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
@@ -234,6 +237,7 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
     } while (0);
     (void)hipFree(dq);
     (void)hipFree(dout);
+    (void)hipFree(dscr);
     return rc;
 }
 
@@ -332,7 +336,7 @@ int ensure_lists(jk_basis_s* h, double tol) {
 
 struct Plan {
     int ndp, dg;
-    size_t off_D, off_J, off_K, off_KT, off_dmax, off_tile, total;
+    size_t off_D, off_J, off_K, off_KT, off_dmax, off_tile, off_scr, total;
     long long tile_elems;
 };
 
@@ -363,6 +367,8 @@ Plan make_plan(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     if (h->list_tol < 0) need = kTileCapElems;
     p.tile_elems = need;
     p.off_tile = off;
+    off += al(static_cast<size_t>(need) * sizeof(double));
+    p.off_scr = off;   // (e0|cd) of pass-evaluated classes: never larger than the tile
     off += al(static_cast<size_t>(need) * sizeof(double));
     p.total = off;
     return p;
@@ -668,6 +674,7 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     double* KTc = o->want_k ? reinterpret_cast<double*>(ws + p.off_KT) : nullptr;
     double* dmax = reinterpret_cast<double*>(ws + p.off_dmax);
     double* tiles = reinterpret_cast<double*>(ws + p.off_tile);
+    double* scratch = reinterpret_cast<double*>(ws + p.off_scr);
     const long long mat = static_cast<long long>(h->nc) * h->nc * p.ndp;
     const long long kmat = static_cast<long long>(h->nc) * h->nc * nd;
     hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, p.ndp, Dc, s);
@@ -729,6 +736,7 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
             ea.ns = h->ns;
             ea.tol = o->schwarz_tol;
             ea.out = tiles;
+            ea.scratch = scratch;
             const double cost_q = L.prim_quartets / static_cast<double>(L.count);
             hipEvent_t ev[2] = {nullptr, nullptr};
             if (h->profiling) {

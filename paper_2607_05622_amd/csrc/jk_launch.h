@@ -34,6 +34,7 @@ struct EriTileArgs {
     int ns;
     double tol;
     double* out;            // [NF][nq]
+    double* scratch;        // [NE*NCD][nq], classes evaluated in passes
 };
 
 struct DigestArgs {
