@@ -61,13 +61,71 @@ def cpu_baseline(w, stride):
                       f"({100 * frac:.2f}%), {dt:.1f} s, scaled by the quartet fraction"}
 
 
+def serve_bench(args):
+    """Poisson request stream over 16 resident molecules (50-730 AO): the
+    continuous-batching server in mixed precision against the plain FP64
+    one-request-at-a-time form, on the same arrivals."""
+    import numpy as np
+    import torch
+
+    from paper_2607_05622_amd import jk, serve, synth
+    dev = torch.device("cuda:0")
+    log("serve: building 16 resident molecules")
+    mols = synth.config4_molecules()
+    bases = [m.basis for m in mols]
+    stream = synth.request_stream(args.requests, 1.0)
+    reqs_d = [synth.request_densities(mols[r["mol"]].meta["orbitals"], r["nd"], r["seed"]) for r in stream]
+    handles = [jk.JKBasis(bb) for bb in bases]
+    # capacity of the plain form: mean service time of one request
+    o64 = jk.jk_default_opts()
+    Dt = [torch.tensor(d, device=dev) for d in reqs_d]
+    for i in range(min(4, len(stream))):
+        jk.jk_build(handles[stream[i]["mol"]].h, Dt[i], opts=o64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, r in enumerate(stream):
+        jk.jk_build(handles[r["mol"]].h, Dt[i], opts=o64)
+    torch.cuda.synchronize()
+    service = (time.perf_counter() - t0) / len(stream)
+    rate = args.rate / service
+    log(f"serve: one-at-a-time FP64 service {service * 1e3:.1f} ms/request -> rate {rate:.1f}/s")
+    rng = np.random.Generator(np.random.PCG64(4_000_000))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(stream)))
+
+    def make():
+        return [serve.Request(i, float(arrivals[i]), r["mol"], Dt[i]) for i, r in enumerate(stream)]
+
+    base = serve.one_at_a_time(handles, make(), o64)
+    log(f"serve: plain FP64 {base['builds_per_s']:.1f} builds/s p50 {base['p50_ms']:.1f} ms")
+    for h in handles:
+        h.close()
+    srv = serve.JKServer(bases, n_slots=4, precision=jk.JK_MIXED, max_batch=16)
+    srv.warm_graphs(max_nd=64)
+    res = srv.run(make(), on_progress=lambda d, n: (d % 20 == 0) and log(f"serve: {d}/{n} done"))
+    srv.close()
+    log(f"serve: mixed server {res['builds_per_s']:.1f} builds/s p50 {res['p50_ms']:.1f} ms")
+    print(json.dumps({"metric": METRIC, "value": res["builds_per_s"], "unit": "builds/s", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "f64+f32", "data": "synthetic",
+                      "config": {"workload": f"served stream: {len(stream)} requests, Poisson at {args.rate}x the "
+                                             "FP64 one-at-a-time capacity, 16 resident molecules "
+                                             f"({min(bb.nbf() for bb in bases)}-{max(bb.nbf() for bb in bases)} AO), "
+                                             "1-64 densities per request"},
+                      "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"], "server": res,
+                      "plain_fp64_one_at_a_time": base,
+                      "speedup_vs_plain_fp64": res["builds_per_s"] / base["builds_per_s"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium", choices=["tiny", "medium", "large"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--serve", action="store_true",
+                    help="serve a Poisson request stream over 16 resident molecules instead")
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--rate", type=float, default=1.0, help="arrival rate / FP64 one-at-a-time capacity")
     ap.add_argument("--cpu-stride", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -82,6 +140,9 @@ def main():
 
     from paper_2607_05622_amd import jk
 
+    if args.serve:
+        serve_bench(args)
+        return
     log(f"workload {args.workload}: generating inputs")
     w = workload(args.workload)
     dev = torch.device("cuda:0")
@@ -93,42 +154,52 @@ def main():
     D = torch.tensor(w.D, dtype=torch.float64, device=dev)
     J = torch.empty_like(D)
     K = torch.empty_like(D)
-    opts = jk.jk_default_opts()
     stream = torch.cuda.current_stream(dev)
-    for i in range(args.warmup):
-        jk.jk_build(b.h, D, J, K, opts, stream)
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-    jk.jk_profile_enable(b.h, True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for i in range(args.steps):
-        jk.jk_build(b.h, D, J, K, opts, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    jk.jk_profile_enable(b.h, False)
-    ms = ev0.elapsed_time(ev1)
+
+    def timed(precision):
+        opts = jk.jk_default_opts(precision=precision)
+        for i in range(args.warmup):
+            jk.jk_build(b.h, D, J, K, opts, stream)
+        torch.cuda.synchronize()
+        jk.jk_profile_enable(b.h, True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for i in range(args.steps):
+            jk.jk_build(b.h, D, J, K, opts, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        jk.jk_profile_enable(b.h, False)
+        ms = ev0.elapsed_time(ev1)
+        st = b.stats()
+        kernels = []
+        for kind, kname in ((0, "eri_tile"), (1, "digest"), (2, "eri_tile_fp32"), (3, "digest_fp32")):
+            for c in range(21):
+                r = jk.jk_profile_read(b.h, kind, c)
+                if r["launches"] > 0:
+                    r.update(kernel=f"{kname}_{CLASS_TAGS[c]}", kind=kname)
+                    kernels.append(r)
+        log(f"{'mixed' if precision else 'fp64'}: {args.steps} steps, {ms / args.steps:.3f} ms/step")
+        return ms, st, kernels
+
+    runs = {}
+    if args.precision in ("fp64", "both"):
+        runs["fp64"] = timed(jk.JK_FP64)
+    if args.precision in ("mixed", "both"):
+        runs["mixed"] = timed(jk.JK_MIXED)
+    head = "fp64" if "fp64" in runs else "mixed"
+    ms, st, kernels = runs[head]
     ms_step = ms / args.steps
-    st = b.stats()
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
-    kernels = []
-    for kind, kname in ((0, "eri_tile"), (1, "digest")):
-        for c in range(21):
-            r = jk.jk_profile_read(b.h, kind, c)
-            if r["launches"] > 0:
-                r.update(kernel=f"{kname}_{CLASS_TAGS[c]}", kind=kname)
-                kernels.append(r)
-    tot_eri_ms = sum(r["ms"] for r in kernels if r["kind"] == "eri_tile")
-    tot_dig_ms = sum(r["ms"] for r in kernels if r["kind"] == "digest")
+    tot_eri_ms = sum(r["ms"] for r in kernels if r["kind"].startswith("eri_tile"))
+    tot_dig_ms = sum(r["ms"] for r in kernels if r["kind"].startswith("digest"))
     dom = max(kernels, key=lambda r: r["ms"])
     per_launch_flops = dom["flops"] / dom["launches"]
     per_launch_ms = dom["ms"] / dom["launches"]
     achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
     builds_s = nd * args.steps / (ms * 1e-3)
     quartets_s = st["quartets"] * args.steps / (ms * 1e-3)
-    eri_tflops = sum(r["flops"] for r in kernels if r["kind"] == "eri_tile") / max(tot_eri_ms, 1e-9) / 1e9
+    eri_tflops = sum(r["flops"] for r in kernels if r["kind"].startswith("eri_tile")) / max(tot_eri_ms, 1e-9) / 1e9
     result = {
         "metric": METRIC,
         "value": builds_s,
@@ -140,11 +211,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.basis.natoms} atoms, {b.nbf} AO ({w.basis.ncart()} Cartesian), "
-                               f"{nd} non-symmetric Laplace pseudo-densities, FP64 path, Schwarz 1e-12",
-                   "nbf": b.nbf, "nd": nd, "precision": args.precision},
+                               f"{nd} non-symmetric Laplace pseudo-densities, {head} path, Schwarz 1e-12",
+                   "nbf": b.nbf, "nd": nd, "precision": head},
         "quartets_per_s": quartets_s,
         "function_quartets_per_s": st["function_quartets"] * args.steps / (ms * 1e-3),
         "primitive_quartets_per_s": st["primitive_quartets"] * args.steps / (ms * 1e-3),
@@ -169,6 +240,13 @@ def main():
         "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / args.steps, 4)
                                for r in sorted(kernels, key=lambda r: -r["ms"])},
     }
+    if "mixed" in runs:
+        mms, mst, mk = runs["mixed"]
+        result["mixed"] = {"builds_per_s": nd * args.steps / (mms * 1e-3), "ms_per_step": mms / args.steps,
+                           "quartets_fp32_fraction": mst["quartets_fp32"] / max(mst["quartets"], 1),
+                           "speedup_vs_fp64": (ms / mms) if head == "fp64" else None,
+                           "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / args.steps, 4)
+                                                  for r in sorted(mk, key=lambda r: -r["ms"])[:12]}}
     b.close()
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a strided sample")

@@ -111,6 +111,47 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
 /* Device bytes one jk_build call with nd densities needs as workspace. */
 size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o);
 
+/* Builds for several molecules at once: nmol handles (same device), density
+ * counts nd[i] and device pointers D[i], J[i], K[i] (host arrays of nmol
+ * entries; matrices as in jk_build).  For every shell-quartet class and
+ * precision tier a single integral launch and a single digestion launch
+ * cover all molecules: a work list of (molecule, class, tier, tile) items
+ * walked by grid-stride blocks, so uneven molecules share the GPU.  Results
+ * are those of nmol separate jk_build calls.  Asynchronous on o->stream;
+ * workspace from jk_batch_workspace_bytes or stream-ordered allocation. */
+int jk_build_batch(int32_t nmol, const jk_basis_t* h, const int32_t* nd, const double* const* D,
+                   double* const* J, double* const* K, const jk_build_opts* o);
+size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t* nd,
+                                const jk_build_opts* o);
+
+/* Schedule autotuning.  Per canonical class the library keeps two launch
+ * parameters: the length cap of a digestion segment (a run of quartets with
+ * one bra pair handled by one workgroup) and the cap on the densities a
+ * digestion workgroup takes at once (1, 2, 4, 8 or 16).  jk_autotune times
+ * every candidate pair on the given build with the event profiler, keeps
+ * the fastest per class, applies it process-wide and, if cache_path is not
+ * NULL, writes it as JSON keyed by GPU architecture and class;
+ * jk_tune_load applies such a file.  Synchronizes o->stream.  Changing the
+ * tunables makes later builds regenerate their cached work plans. */
+int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
+                const jk_build_opts* o, const char* cache_path);
+int jk_tune_load(const char* path);
+int jk_tune_set(int32_t cls, int32_t seg_max, int32_t g_max);
+int jk_tune_get(int32_t cls, int32_t* seg_max, int32_t* g_max);
+
+/* HIP graph of one build, for callers that replay the same build shape
+ * (serving loops with fixed per-slot buffers).  jk_graph_create captures
+ * jk_build(h, nd, D, J, K, o) into an executable graph; the pointers D, J, K
+ * and o->workspace (required: nothing is allocated inside the graph) are
+ * baked in, so each replay reads the current contents of D and overwrites J
+ * and K.  o->stream is ignored; profiling must be off.  jk_graph_launch
+ * replays it on `stream` (hipStream_t, NULL = default). */
+typedef struct jk_graph_s* jk_graph_t;
+int jk_graph_create(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
+                    const jk_build_opts* o, jk_graph_t* out);
+int jk_graph_launch(jk_graph_t g, void* stream);
+void jk_graph_destroy(jk_graph_t g);
+
 /* Release everything the handle owns.  NULL-safe.  The caller must have
  * synchronized every stream that used the handle. */
 void jk_destroy(jk_basis_t h);
@@ -139,8 +180,9 @@ int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
  * jk_build on h record a HIP event pair around each integral and digestion
  * launch, on the build's stream; jk_profile_read synchronizes those events
  * and returns, per kernel, totals since the last read, then clears them.
- * kind 0 = integral (ERI tile) kernel, 1 = digestion kernel; cls = canonical
- * class index 0..20.  out[0] total milliseconds, out[1] launches,
+ * kind 0 = integral (ERI tile) kernel, 1 = digestion kernel, 2 and 3 the
+ * same for the FP32 tier of JK_MIXED builds; cls = canonical class index
+ * 0..20.  out[0] total milliseconds, out[1] launches,
  * out[2] algorithmic flops, out[3] shell quartets, out[4] bytes written
  * (integral tiles) or read (tiles, digestion).  Not for concurrent builds. */
 int jk_profile_enable(jk_basis_t h, int32_t on);

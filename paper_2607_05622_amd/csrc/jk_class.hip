@@ -12,29 +12,40 @@ namespace jk {
 #define JK_PASTE2(a, b) a##b
 #define JK_PASTE(a, b) JK_PASTE2(a, b)
 
-#define JK_DEFINE(idx, tag, la, lb, lc, ld)                                                       \
-    static_assert(idx >= 0, "");                                                                  \
-    hipError_t JK_PASTE(launch_eri_tile_c, idx)(const EriTileArgs& a, hipStream_t s) {            \
-        const unsigned g = static_cast<unsigned>((a.nq + 255) / 256);                             \
-        if constexpr (Eri##tag<double>::kSplit)                                                   \
-            hipLaunchKernelGGL(k_eri_tile_split<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);  \
-        else                                                                                      \
-            hipLaunchKernelGGL(k_eri_tile<Eri##tag<double>>, dim3(g), dim3(256), 0, s, a);        \
-        return hipGetLastError();                                                                 \
-    }                                                                                             \
-    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s) {               \
-        constexpr int NA = (la + 1) * (la + 2) / 2, NB = (lb + 1) * (lb + 2) / 2;                  \
-        const int W = a.colAw + a.colBw;                                                          \
-        const size_t lds = sizeof(double) * ((a.want_k ? 2 * (NA + NB) * a.G * W : 0) +           \
-                                             (a.want_j ? NA * NB * a.G : 0));                     \
-        const unsigned g = static_cast<unsigned>(8 * ((a.nseg + 7) / 8) * a.ngroups);             \
-        hipLaunchKernelGGL((k_digest<la, lb, lc, ld>), dim3(g), dim3(256), lds, s, a);            \
-        return hipGetLastError();                                                                 \
-    }                                                                                             \
-    hipError_t JK_PASTE(digest_prepare_c, idx)(size_t lds_bytes) {                                \
-        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld>),       \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,                    \
-                                   static_cast<int>(lds_bytes));                                  \
+// Integral launches are grid-stride: enough blocks to fill the chip, each
+// walking the item blocks of the launch.
+constexpr long long kEriGridCap = 256 * 8;
+
+template <class C, typename R>
+hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
+    const unsigned g = static_cast<unsigned>(a.nblocks < kEriGridCap ? a.nblocks : kEriGridCap);
+    hipLaunchKernelGGL((k_eri_tile<C, R>), dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int la, int lb, int lc, int ld, typename TT>
+hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_digest<la, lb, lc, ld, TT>), dim3(a.nblocks), dim3(256), a.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+#define JK_DEFINE(idx, tag, la, lb, lc, ld)                                                        \
+    hipError_t JK_PASTE(launch_eri_tile_c, idx)(const EriTileArgs& a, hipStream_t s, int fp32) {   \
+        return fp32 ? launch_eri_tpl<Eri##tag<float>, float>(a, s)                                 \
+                    : launch_eri_tpl<Eri##tag<double>, double>(a, s);                              \
+    }                                                                                              \
+    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s, int fp32) {      \
+        return fp32 ? launch_digest_tpl<la, lb, lc, ld, float>(a, s)                               \
+                    : launch_digest_tpl<la, lb, lc, ld, double>(a, s);                             \
+    }                                                                                              \
+    hipError_t JK_PASTE(digest_prepare_c, idx)(size_t lds_bytes) {                                 \
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld, double>), \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,             \
+                                           static_cast<int>(lds_bytes));                           \
+        if (e != hipSuccess) return e;                                                             \
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld, float>), \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                                   static_cast<int>(lds_bytes));                                   \
     }
 
 #define JK_SELECT(idx, tag, la, lb, lc, ld) JK_SELECT_##idx(idx, tag, la, lb, lc, ld)

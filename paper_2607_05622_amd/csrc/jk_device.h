@@ -68,6 +68,75 @@ __device__ __forceinline__ void boys_f64(double T, double pref, const double* __
     for (int m = 0; m <= L; ++m) F[m] *= pref;
 }
 
+// FP32 tier: F_m(T) in FP32 inside the table range (five-term Taylor
+// expansion about the nearest grid point, exp(-T) likewise, downward
+// recursion), the FP64 asymptotic form beyond it; the FP64 prefactor is
+// applied in FP64 before rounding to FP32.
+template <int L>
+__device__ __forceinline__ void boys_f32(double T, double pref, const float* __restrict__ tab,
+                                         float* __restrict__ F) {
+    if (T < kBoysTMax) {
+        const int i = static_cast<int>(T * kBoysInvStep + 0.5);
+        const float x = static_cast<float>(static_cast<double>(i) * (1.0 / kBoysInvStep) - T);
+        const float* __restrict__ r = tab + i * kBoysCols;
+        float f = r[L + 4];
+        f = fmaf(f, x * 0.25f, r[L + 3]);
+        f = fmaf(f, x * (1.0f / 3), r[L + 2]);
+        f = fmaf(f, x * 0.5f, r[L + 1]);
+        f = fmaf(f, x, r[L]);
+        F[L] = f;
+        if constexpr (L > 0) {
+            float e = 1.0f / 120;
+            e = fmaf(e, x, 1.0f / 24);
+            e = fmaf(e, x, 1.0f / 6);
+            e = fmaf(e, x, 0.5f);
+            e = fmaf(e, x, 1.0f);
+            e = fmaf(e, x, 1.0f);
+            e *= r[kBoysCols - 1];
+            const float t2 = static_cast<float>(T + T);
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = fmaf(t2, F[m + 1], e) * (1.0f / static_cast<float>(2 * m + 1));
+        }
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] = static_cast<float>(static_cast<double>(F[m]) * pref);
+    } else {
+        double Fd[L + 1];
+        const double it = 1.0 / T;
+        double f = sqrt(0.78539816339744830962 * it);
+        Fd[0] = f;
+        const double h = 0.5 * it;
+#pragma unroll
+        for (int m = 0; m < L; ++m) {
+            f *= static_cast<double>(2 * m + 1) * h;
+            Fd[m + 1] = f;
+        }
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] = static_cast<float>(Fd[m] * pref);
+    }
+}
+
+// Boys values of the working precision R.
+template <int L, typename R>
+__device__ __forceinline__ void boys_r(double T, double pref, const EriTileArgs& a, R* F) {
+    if constexpr (sizeof(R) == 8) boys_f64<L>(T, pref, a.boys, F);
+    else boys_f32<L>(T, pref, a.boys32, F);
+}
+
+template <typename R>
+__device__ __forceinline__ void coef_to(const VrrCoef<double>& k, VrrCoef<R>& o) {
+    for (int i = 0; i < 3; ++i) {
+        o.PA[i] = static_cast<R>(k.PA[i]);
+        o.WP[i] = static_cast<R>(k.WP[i]);
+        o.QC[i] = static_cast<R>(k.QC[i]);
+        o.WQ[i] = static_cast<R>(k.WQ[i]);
+    }
+    o.rp = static_cast<R>(k.rp);
+    o.rq = static_cast<R>(k.rq);
+    o.o2p = static_cast<R>(k.o2p);
+    o.o2q = static_cast<R>(k.o2q);
+    o.o2pq = static_cast<R>(k.o2pq);
+}
+
 // Per-primitive-quartet quantities of the vertical recurrence.
 __device__ __forceinline__ void prim_setup(const PrimPair& P, const PrimPair& Q, const double* A,
                                            const double* C, VrrCoef<double>& k, double& T,
@@ -117,24 +186,36 @@ __device__ __forceinline__ bool keep_quartet(const PairInfo& P, const PairInfo& 
 
 // ------------------------------------------------------------ ERI tile ---
 
-template <class C>
-__global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
-    const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= a.nq) return;
-    const int2 bk = a.quartets[q];
-    const PairInfo& P = a.pairs[bk.x];
-    const PairInfo& Q = a.pairs[bk.y];
-    double* __restrict__ out = a.out + q;
-    if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) {
+// Block blk of a launch belongs to the last item whose first block is <= blk.
+__device__ __forceinline__ int find_item(const EriItem* __restrict__ items, int n, long long blk) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].blk0 <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One contracted quartet, one lane.  R = double (FP64 tier) or float (FP32
+// tier; the tile is stored as float).
+template <class C, typename R>
+__device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, const EriItem& it, long long q) {
+    const int2 bk = it.quartets[q];
+    const PairInfo& P = m.pairs[bk.x];
+    const PairInfo& Q = m.pairs[bk.y];
+    const long long nq = it.n;
+    R* __restrict__ out = static_cast<R*>(a.tiles) + it.tile_off + q;
+    if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
-        for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * a.nq] = 0.0;
+        for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
         return;
     }
-    double acc[C::NACC];
+    R acc[C::NACC];
 #pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    const PrimPair* __restrict__ pb = a.prims + P.prim_off;
-    const PrimPair* __restrict__ pk = a.prims + Q.prim_off;
+    for (int i = 0; i < C::NACC; ++i) acc[i] = R(0);
+    const PrimPair* __restrict__ pb = m.prims + P.prim_off;
+    const PrimPair* __restrict__ pk = m.prims + Q.prim_off;
     const int nb = P.nprim, nk = Q.nprim;
 #pragma unroll 1
     for (int i = 0; i < nb; ++i) {
@@ -142,31 +223,38 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
 #pragma unroll 1
         for (int j = 0; j < nk; ++j) {
             const PrimPair qq = pk[j];
-            VrrCoef<double> k;
+            VrrCoef<double> kd;
             double T, pref;
-            prim_setup(pp, qq, P.A, Q.A, k, T, pref);
-            double F[C::L + 1];
-            boys_f64<C::L>(T, pref, a.boys, F);
-            C::vrr(F, k, acc);
+            prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
+            R F[C::L + 1];
+            boys_r<C::L, R>(T, pref, a, F);
+            if constexpr (sizeof(R) == 8) {
+                C::vrr(F, kd, acc);
+            } else {
+                VrrCoef<R> k;
+                coef_to(kd, k);
+                C::vrr(F, k, acc);
+            }
         }
     }
-    const long long nq = a.nq;
-    C::hrr(acc, P.AB, Q.AB, [&](int f, double v) { out[static_cast<long long>(f) * nq] = v; });
+    const R AB[3] = {R(P.AB[0]), R(P.AB[1]), R(P.AB[2])};
+    const R CD[3] = {R(Q.AB[0]), R(Q.AB[1]), R(Q.AB[2])};
+    C::hrr(acc, AB, CD, [&](int f, R v) { out[static_cast<long long>(f) * nq] = v; });
 }
 
 // High angular momentum: passes over groups of bra components.  Each pass
 // runs the primitive loop for its own part of the vertical recurrence, keeps
 // only its group's accumulators live, applies HRR-CD and parks (e0|cd) in
 // scratch; HRR-AB then assembles the tile one ket function pair at a time.
-template <class C, int G>
-__device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const PairInfo& P, const PairInfo& Q,
-                                               double* __restrict__ scr, long long nq) {
+template <class C, typename R, int G>
+__device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDesc& m, const PairInfo& P,
+                                               const PairInfo& Q, R* __restrict__ scr, long long nq) {
     if constexpr (G < C::NG) {
-        double acc[C::GMAX];
+        R acc[C::GMAX];
 #pragma unroll
-        for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
-        const PrimPair* __restrict__ pb = a.prims + P.prim_off;
-        const PrimPair* __restrict__ pk = a.prims + Q.prim_off;
+        for (int i = 0; i < C::GN[G]; ++i) acc[i] = R(0);
+        const PrimPair* __restrict__ pb = m.prims + P.prim_off;
+        const PrimPair* __restrict__ pk = m.prims + Q.prim_off;
         const int nb = P.nprim, nk = Q.nprim;
 #pragma unroll 1
         for (int i = 0; i < nb; ++i) {
@@ -174,58 +262,65 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const PairI
 #pragma unroll 1
             for (int j = 0; j < nk; ++j) {
                 const PrimPair qq = pk[j];
-                VrrCoef<double> k;
+                VrrCoef<double> kd;
                 double T, pref;
-                prim_setup(pp, qq, P.A, Q.A, k, T, pref);
-                double F[C::L + 1];
-                boys_f64<C::L>(T, pref, a.boys, F);
-                C::template vrr_group<G>(F, k, acc);
+                prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
+                R F[C::L + 1];
+                boys_r<C::L, R>(T, pref, a, F);
+                if constexpr (sizeof(R) == 8) {
+                    C::template vrr_group<G>(F, kd, acc);
+                } else {
+                    VrrCoef<R> k;
+                    coef_to(kd, k);
+                    C::template vrr_group<G>(F, k, acc);
+                }
             }
         }
-        C::template hrrcd_group<G>(acc, Q.AB, [&](int idx, double v) { scr[static_cast<long long>(idx) * nq] = v; });
-        eri_split_pass<C, G + 1>(a, P, Q, scr, nq);
+        const R CD[3] = {R(Q.AB[0]), R(Q.AB[1]), R(Q.AB[2])};
+        C::template hrrcd_group<G>(acc, CD, [&](int idx, R v) { scr[static_cast<long long>(idx) * nq] = v; });
+        eri_split_pass<C, R, G + 1>(a, m, P, Q, scr, nq);
     }
 }
 
-template <class C>
-__global__ __launch_bounds__(256) void k_eri_tile_split(EriTileArgs a) {
-    const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= a.nq) return;
-    const int2 bk = a.quartets[q];
-    const PairInfo& P = a.pairs[bk.x];
-    const PairInfo& Q = a.pairs[bk.y];
-    double* __restrict__ out = a.out + q;
-    const long long nq = a.nq;
-    if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) {
+template <class C, typename R>
+__device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDesc& m, const EriItem& it,
+                                              long long q) {
+    const int2 bk = it.quartets[q];
+    const PairInfo& P = m.pairs[bk.x];
+    const PairInfo& Q = m.pairs[bk.y];
+    const long long nq = it.n;
+    R* __restrict__ out = static_cast<R*>(a.tiles) + it.tile_off + q;
+    if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
-        for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = 0.0;
+        for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
         return;
     }
-    double* __restrict__ scr = a.scratch + q;
-    eri_split_pass<C, 0>(a, P, Q, scr, nq);
+    R* __restrict__ scr = static_cast<R*>(a.scratch) + it.tile_off + q;
+    eri_split_pass<C, R, 0>(a, m, P, Q, scr, nq);
+    const R AB[3] = {R(P.AB[0]), R(P.AB[1]), R(P.AB[2])};
 #pragma unroll 1
     for (int cd = 0; cd < C::NCD; ++cd) {
-        C::hrrab([&](int e) -> double { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, P.AB,
-                 [&](int ab, double v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = v; });
+        C::hrrab([&](int e) -> R { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, AB,
+                 [&](int ab, R v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = v; });
+    }
+}
+
+// Grid-stride over the blocks of every item of the launch (all molecules of
+// a batch for one class and tier).
+template <class C, typename R>
+__global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
+    for (long long blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
+        const EriItem it = a.items[find_item(a.items, a.nitems, blk)];
+        const long long q = (blk - it.blk0) * blockDim.x + threadIdx.x;
+        if (q >= it.n) continue;
+        const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
+        if constexpr (C::kSplit) eri_one_split<C, R>(a, m, it, q);
+        else eri_one<C, R>(a, m, it, q);
     }
 }
 
 // -------------------------------------------------------------- digest ---
 
-// One workgroup per (segment, density group).  A segment is a run of
-// quartets of one class sharing the bra pair (a b); its contributions to K
-// fall in four strips -- rows of a and b (K_ac, K_ad, K_bc, K_bd) and columns
-// of a and b (K_ca, K_da, K_cb, K_db) -- restricted to the function windows of
-// the ket shells' angular momenta.  The strips accumulate in LDS and are
-// flushed once with coalesced FP64 atomics: rows into K [x][i][j], columns
-// into KT [x][i][j] (K_{row,col} gets KT[col][row]).  J_ab is reduced over
-// the segment in registers and LDS; J_cd goes straight to J [i][j][x],
-// coalesced over the density lanes.  Scatter of every distinct index
-// permutation with the canonical-fold multiplicity w (Sect. 3, Eq.
-// (quartet_scatter)).
-//
-// Thread t handles density x0 + (t % G) for quartets slot, slot + S, ...
-// (S = blockDim / G); lanes that share a quartet read the same tile words.
 // Digestion of one quartet for one density; OUTER is the unroll pragma of
 // the loops over output elements (full unroll keeps a register tile in
 // registers, no unroll keeps large tiles streaming from memory).
@@ -319,7 +414,7 @@ _Pragma("unroll") \
             } \
         
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, typename TT>
 __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
     extern __shared__ double lds[];
     constexpr int NA = (LA + 1) * (LA + 2) / 2, NB = (LB + 1) * (LB + 2) / 2;
@@ -327,16 +422,25 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
     constexpr int NF = NA * NB * NC * ND;
     constexpr int R = 2 * (NA + NB);
     constexpr bool kRegTile = NF <= 36;
-    const int G = a.G;
-    // blocks of one segment share an XCD (block b runs on XCD b % 8)
+    // items are spread over the XCDs round-robin (item i on XCD i % 8, block
+    // b runs on XCD b % 8), so the density groups of one item share an L2
     const int b = blockIdx.x;
     const int xcd = b & 7, kk = b >> 3;
-    const int seg = (kk / a.ngroups) * 8 + xcd;
-    const int grp = kk - (kk / a.ngroups) * a.ngroups;
-    if (seg >= a.nseg) return;
+    if (xcd >= a.nitems) return;
+    int lo = 0, hi = (a.nitems - 1 - xcd) >> 3;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.items[xcd + 8 * mid].kstart <= kk) lo = mid;
+        else hi = mid - 1;
+    }
+    const DigItem it = a.items[xcd + 8 * lo];
+    const int grp = kk - it.kstart;
+    if (grp < 0 || grp >= it.ngroups) return;
+    const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
+    const int G = it.G;
     const int x0 = grp * G;
-    const int gn = min(G, a.nd - x0);
-    const int W = a.colAw + a.colBw;
+    const int gn = min(G, m.nd - x0);
+    const int W = it.colAw + it.colBw;
     const int nstrip = a.want_k ? R * G * W : 0;
     double* __restrict__ strips = lds;            // [R][G][W]
     double* __restrict__ jab = lds + nstrip;      // [NA*NB][G]
@@ -344,45 +448,47 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
     for (int i = threadIdx.x; i < nlds; i += blockDim.x) lds[i] = 0.0;
     __syncthreads();
 
-    const int2 sg = a.segs[seg];
-    const long long q0 = sg.x - a.qbase;
+    const int2 sg = it.seg;
+    const long long q0 = sg.x - it.chunk_q0;     // tile index of the segment's first quartet
     const int slots = blockDim.x / G;
     const int slot = threadIdx.x / G, g = threadIdx.x - slot * G;
     const bool active = slot < slots && g < gn;
-    const PairInfo& P = a.pairs[a.quartets[q0].x];
+    const int2* __restrict__ quartets = it.quartets + it.chunk_q0;
+    const PairInfo& P = m.pairs[quartets[q0].x];
     const int fa = P.fa, fb = P.fb;
-    const long long nc = a.nc, ndp = a.ndp, nq = a.nq;
-    auto lcol = [&](int col) { return (col >= a.colA0 && col < a.colA0 + a.colAw) ? col - a.colA0 : a.colAw + (col - a.colB0); };
+    const long long nc = m.nc, ndp = m.nd, nq = it.chunk_n;
+    const int colA0 = it.colA0, colAw = it.colAw, colB0 = it.colB0;
+    auto lcol = [&](int col) { return (col >= colA0 && col < colA0 + colAw) ? col - colA0 : colAw + (col - colB0); };
     double jacc[NA * NB];
 #pragma unroll
     for (int e = 0; e < NA * NB; ++e) jacc[e] = 0.0;
     if (active) {
         const int x = x0 + g;
-        const double* __restrict__ Dm = a.D + x;
+        const double* __restrict__ Dm = m.D + x;
         auto Dv = [&](int r, int c) -> double { return Dm[(r * nc + c) * ndp]; };
-        double* __restrict__ Jm = a.J + x;
+        double* __restrict__ Jm = m.J + x;
         double* __restrict__ sA = strips + static_cast<long long>(g) * W;   // row block 0, density g
         auto S = [&](int row, int col) -> double* { return sA + static_cast<long long>(row) * G * W + col; };
 #pragma unroll 1
         for (int qi = slot; qi < sg.y; qi += slots) {
             const long long q = q0 + qi;
-            const int2 bk = a.quartets[q];
-            const PairInfo& Q = a.pairs[bk.y];
-            if (!keep_quartet(P, Q, a.dmax, a.ns, a.tol)) continue;
+            const int2 bk = quartets[q];
+            const PairInfo& Q = m.pairs[bk.y];
+            if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) continue;
             double w = 1.0;
             if (P.sa == P.sb) w *= 0.5;
             if (Q.sa == Q.sb) w *= 0.5;
             if (bk.x == bk.y) w *= 0.5;
-            const double* __restrict__ tg = a.tiles + q;
+            const TT* __restrict__ tg = static_cast<const TT*>(a.tiles) + it.tile_off + q;
             double treg[kRegTile ? NF : 1];
             if constexpr (kRegTile) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) treg[f] = tg[f * nq];
+                for (int f = 0; f < NF; ++f) treg[f] = static_cast<double>(tg[f * nq]);
             }
             auto I = [&](int i, int j, int k, int l) -> double {
                 const int f = ((i * NB + j) * NC + k) * ND + l;
                 if constexpr (kRegTile) return treg[f];
-                else return tg[static_cast<long long>(f) * nq];
+                else return static_cast<double>(tg[static_cast<long long>(f) * nq]);
             };
             const int fc = Q.fa, fd = Q.fb;
             const int cc = lcol(fc), cd = lcol(fd);
@@ -408,12 +514,12 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
             if (gg >= gn) continue;
             const double v = strips[idx];
             if (v == 0.0) continue;
-            const int col = c < a.colAw ? a.colA0 + c : a.colB0 + (c - a.colAw);
+            const int col = c < colAw ? colA0 + c : it.colB0 + (c - colAw);
             const long long x = x0 + gg;
-            if (r < NA) unsafeAtomicAdd(a.K + x * mat + (fa + r) * nc + col, v);
-            else if (r < NA + NB) unsafeAtomicAdd(a.K + x * mat + (fb + r - NA) * nc + col, v);
-            else if (r < 2 * NA + NB) unsafeAtomicAdd(a.KT + x * mat + (fa + r - NA - NB) * nc + col, v);
-            else unsafeAtomicAdd(a.KT + x * mat + (fb + r - 2 * NA - NB) * nc + col, v);
+            if (r < NA) unsafeAtomicAdd(m.K + x * mat + (fa + r) * nc + col, v);
+            else if (r < NA + NB) unsafeAtomicAdd(m.K + x * mat + (fb + r - NA) * nc + col, v);
+            else if (r < 2 * NA + NB) unsafeAtomicAdd(m.KT + x * mat + (fa + r - NA - NB) * nc + col, v);
+            else unsafeAtomicAdd(m.KT + x * mat + (fb + r - 2 * NA - NB) * nc + col, v);
         }
     }
     if (a.want_j) {
@@ -421,7 +527,7 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
             const int e = idx / G, gg = idx - e * G;
             if (gg >= gn) continue;
             const int i = e / NB, j = e - i * NB;
-            unsafeAtomicAdd(a.J + ((fa + i) * nc + fb + j) * ndp + x0 + gg, jab[idx]);
+            unsafeAtomicAdd(m.J + ((fa + i) * nc + fb + j) * ndp + x0 + gg, jab[idx]);
         }
     }
 }

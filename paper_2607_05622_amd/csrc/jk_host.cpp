@@ -95,20 +95,33 @@ const double kSphD[5][6] = {
 
 int class_nf(int cls) { return kClassCost[cls].nfunc; }
 
-// Runs of quartets sharing a bra pair, capped in length: the unit of work of
-// the digestion kernel.
-constexpr int kSegMax = 1024;
-
-struct Chunk {
-    int s0, s1;          // segments [s0, s1)
-    long long q0, q1;    // quartets [q0, q1) of the class list
+// Schedule tunables per class (process-wide; chosen by jk_autotune): the
+// length cap of a digestion segment (a run of quartets sharing a bra pair,
+// the unit of work of a digestion workgroup) and the cap on the densities a
+// digestion workgroup handles at once.
+struct Tune {
+    int seg_max = 1024;
+    int g_max = 16;
 };
+std::mutex g_tune_mu;
+Tune g_tune[kNumClass];
+int g_tune_gen = 0;
 
+Tune tune_of(int cls) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tune[cls];
+}
+
+
+// A class list holds its FP64-tier quartets (Q_ab Q_cd >= fp32 bound) first
+// and its FP32-tier quartets after them; segments never straddle the two.
 struct ClassList {
     long long count = 0;
-    double prim_quartets = 0;   // sum of nprim_bra * nprim_ket
+    long long n64 = 0;               // quartets of the FP64 tier (list prefix)
+    int nseg64 = 0;                  // segments of the FP64 tier (prefix of segs)
+    double prim_quartets[2] = {0, 0};   // sum of nprim_bra * nprim_ket per tier
     int2* dev = nullptr;
-    std::vector<int2> segs;     // (first quartet, count)
+    std::vector<int2> segs;          // (first quartet, count)
     int2* dev_segs = nullptr;
 };
 
@@ -116,6 +129,11 @@ struct ClassList {
 const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
 
 }  // namespace
+
+namespace {
+struct CachedPlan;
+void free_plan(CachedPlan* cp);
+}
 
 struct jk_basis_s {
     int device = 0;
@@ -141,11 +159,15 @@ struct jk_basis_s {
     // freed, because builds on other streams may still read them)
     std::mutex mu;
     double list_tol = -1.0;
+    double list_bound = 1e-6;          // FP32-tier bound the lists are partitioned with
+    float* d_boys32 = nullptr;
     ClassList lists[kNumClass];
     std::vector<int2*> retired;
     int lds_cap = 65536;               // dynamic LDS bytes per workgroup
     int lw_off[kMaxL + 1] = {}, lw_len[kMaxL + 1] = {};   // Cartesian function window per l
-    size_t prepared[kNumClass] = {};   // LDS attribute already granted per class
+    int list_gen = 0;                  // bumped whenever the lists are rebuilt
+    int tune_gen = -1;                 // tunables the lists were segmented with
+    std::vector<CachedPlan*> plans;    // single-molecule plans (freed by jk_destroy)
     double stats[6] = {0, 0, 0, 0, 0, 0};
     // measurement: event pairs around integral / digestion launches
     struct ProfRec {
@@ -155,7 +177,7 @@ struct jk_basis_s {
     };
     bool profiling = false;
     std::vector<ProfRec> prof;
-    double prof_acc[2][kNumClass][5] = {};
+    double prof_acc[4][kNumClass][5] = {};
 
     ~jk_basis_s() {
         int cur = 0;
@@ -164,6 +186,7 @@ struct jk_basis_s {
         (void)hipFree(d_pairs);
         (void)hipFree(d_prims);
         (void)hipFree(d_boys);
+        (void)hipFree(d_boys32);
         (void)hipFree(d_cmap);
         (void)hipFree(d_umap);
         (void)hipFree(d_shell_f0);
@@ -201,25 +224,37 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
     int2* dq = nullptr;
     double* dout = nullptr;
     double* dscr = nullptr;
+    EriItem* ditem = nullptr;
     HIPC(hipMalloc(&dq, nq * sizeof(int2)));
     HIPC(hipMalloc(&dout, nq * NF * sizeof(double)));
     HIPC(hipMalloc(&dscr, nq * NF * sizeof(double)));
+    HIPC(hipMalloc(&ditem, sizeof(EriItem)));
     int rc = JK_OK;
     do {
-        if (hipMemcpy(dq, quartets.data(), nq * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+        EriItem it{};
+        it.quartets = dq;
+        it.n = nq;
+        it.tile_off = 0;
+        it.blk0 = 0;
+        it.mol = 0;
+        if (hipMemcpy(dq, quartets.data(), nq * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ditem, &it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess) {
             rc = fail(JK_EDEVICE, "eval_tiles: copy in failed");
             break;
         }
         EriTileArgs a{};
-        a.quartets = dq;
-        a.nq = nq;
-        a.pairs = h->d_pairs;
-        a.prims = h->d_prims;
+        a.items = ditem;
+        a.nitems = 1;
+        a.nblocks = (nq + 255) / 256;
+        a.mol0.pairs = h->d_pairs;
+        a.mol0.prims = h->d_prims;
+        a.mol0.dmax = nullptr;
+        a.mol0.ns = h->ns;
+        a.mols = nullptr;
         a.boys = h->d_boys;
-        a.dmax = nullptr;
-        a.ns = h->ns;
+        a.boys32 = h->d_boys32;
         a.tol = 0.0;
-        a.out = dout;
+        a.tiles = dout;
         a.scratch = dscr;
         hipError_t e = launch_eri_tile(cls, a, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -238,6 +273,7 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
     (void)hipFree(dq);
     (void)hipFree(dout);
     (void)hipFree(dscr);
+    (void)hipFree(ditem);
     return rc;
 }
 
@@ -269,7 +305,7 @@ int compute_schwarz(jk_basis_s* h) {
 
 // Build the class-bucketed quartet lists kept by Q_ab Q_cd >= tol.  Within a
 // class: bra pair outer, ket pairs in index order.
-int build_lists(jk_basis_s* h, double tol) {
+int build_lists(jk_basis_s* h, double tol, double bound) {
     ClassList fresh[kNumClass];
     for (int X = 0; X < kNumPairClass; ++X) {
         for (int Y = 0; Y <= X; ++Y) {
@@ -279,9 +315,9 @@ int build_lists(jk_basis_s* h, double tol) {
             // ket pairs sorted by Q, descending, to stop early
             std::vector<int> ks(ket);
             std::sort(ks.begin(), ks.end(), [&](int u, int v) { return h->pairs[u].q > h->pairs[v].q; });
-            std::vector<int2> out;
+            std::vector<int2> tier[2];
             std::vector<int> keep;
-            double primq = 0;
+            double primq[2] = {0, 0};
             for (int b : bra) {
                 const double qb = h->pairs[b].q;
                 keep.clear();
@@ -292,19 +328,29 @@ int build_lists(jk_basis_s* h, double tol) {
                 }
                 std::sort(keep.begin(), keep.end());
                 for (int k : keep) {
-                    out.push_back(make_int2(b, k));
-                    primq += static_cast<double>(h->pairs[b].nprim) * h->pairs[k].nprim;
+                    const int t = qb * h->pairs[k].q < bound ? 1 : 0;
+                    tier[t].push_back(make_int2(b, k));
+                    primq[t] += static_cast<double>(h->pairs[b].nprim) * h->pairs[k].nprim;
                 }
             }
+            std::vector<int2> out(tier[0]);
+            out.insert(out.end(), tier[1].begin(), tier[1].end());
             fresh[cls].count = static_cast<long long>(out.size());
-            fresh[cls].prim_quartets = primq;
-            // segments: bra-pair runs of at most kSegMax quartets
+            fresh[cls].n64 = static_cast<long long>(tier[0].size());
+            fresh[cls].prim_quartets[0] = primq[0];
+            fresh[cls].prim_quartets[1] = primq[1];
+            // segments: bra-pair runs of at most seg_max quartets, per tier
+            const int seg_max = tune_of(cls).seg_max;
             auto& segs = fresh[cls].segs;
-            for (size_t q = 0; q < out.size();) {
-                size_t e = q + 1;
-                while (e < out.size() && out[e].x == out[q].x && static_cast<int>(e - q) < kSegMax) ++e;
-                segs.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
-                q = e;
+            for (int t = 0; t < 2; ++t) {
+                const size_t lo = t ? tier[0].size() : 0, hi = t ? out.size() : tier[0].size();
+                for (size_t q = lo; q < hi;) {
+                    size_t e = q + 1;
+                    while (e < hi && out[e].x == out[q].x && static_cast<int>(e - q) < seg_max) ++e;
+                    segs.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
+                    q = e;
+                }
+                if (t == 0) fresh[cls].nseg64 = static_cast<int>(segs.size());
             }
             if (!out.empty()) {
                 int rc = upload(&fresh[cls].dev, out);
@@ -325,54 +371,213 @@ int build_lists(jk_basis_s* h, double tol) {
         h->lists[c] = fresh[c];
     }
     h->list_tol = tol;
+    h->list_bound = bound;
+    h->list_gen++;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        h->tune_gen = g_tune_gen;
+    }
     return JK_OK;
 }
 
-int ensure_lists(jk_basis_s* h, double tol) {
+// Lists usable for a build with tolerance tol and, in mixed mode, FP32 bound
+// `bound` (bound < 0: any partition will do).
+int ensure_lists(jk_basis_s* h, double tol, double bound) {
     std::lock_guard<std::mutex> g(h->mu);
-    if (h->list_tol >= 0 && h->list_tol <= tol) return JK_OK;
-    return build_lists(h, tol);
+    const bool tol_ok = h->list_tol >= 0 && h->list_tol <= tol;
+    const bool bound_ok = bound < 0 || h->list_bound == bound;
+    int tg;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tg = g_tune_gen;
+    }
+    if (tol_ok && bound_ok && h->tune_gen == tg) return JK_OK;
+    return build_lists(h, tol_ok ? h->list_tol : tol, bound < 0 ? h->list_bound : bound);
 }
 
-struct Plan {
-    int ndp, dg;
-    size_t off_D, off_J, off_K, off_KT, off_dmax, off_tile, off_scr, total;
-    long long tile_elems;
+// ----------------------------------------------------------- work plans ---
+
+// One class and tier of a build: an integral launch over eri items and a
+// digestion launch over dig items, all molecules together.
+struct LaunchRec {
+    int cls = 0, fp32 = 0;
+    int eri0 = 0, neri = 0;
+    long long eri_blocks = 0;
+    int dig0 = 0, ndig = 0;
+    unsigned dig_blocks = 0;
+    size_t lds = 0;
+    double eri_flops = 0, dig_flops = 0, quartets = 0, tile_bytes = 0;
+    int kcount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
-Plan make_plan(const jk_basis_s* h, int nd, const jk_build_opts* o) {
-    Plan p{};
-    p.dg = 1;
-    p.ndp = nd;
-    const size_t mat = static_cast<size_t>(h->nc) * h->nc * p.ndp * sizeof(double);
-    auto al = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
-    size_t off = 0;
-    p.off_D = off;
-    off += al(mat);
-    p.off_J = off;
-    if (o->want_j) off += al(mat);
-    const size_t kmat = static_cast<size_t>(h->nc) * h->nc * nd * sizeof(double);
-    p.off_K = off;
-    if (o->want_k) off += al(kmat);
-    p.off_KT = off;
-    if (o->want_k) off += al(kmat);
-    p.off_dmax = off;
-    off += al(static_cast<size_t>(h->ns) * h->ns * sizeof(double));
-    // tile buffer: the largest class volume, capped
-    long long need = 1296;
+struct MolRun {
+    jk_basis_s* h;
+    int nd;
+};
+
+struct WorkPlan {
+    std::vector<EriItem> eri;
+    std::vector<DigItem> dig;
+    std::vector<LaunchRec> launches;
+    long long tile_elems = 1296;
+    double stats[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// Split every class list (per tier) of every molecule into tile items of
+// whole segments and digestion items (one per segment), packing items into
+// launches whose tiles fit a buffer of cap elements.
+int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_cap, long long cap, WorkPlan& wp) {
+    const bool mixed = o->precision == JK_MIXED;
     for (int c = 0; c < kNumClass; ++c) {
-        const long long v = h->lists[c].count * class_nf(c);
-        need = std::max(need, std::min(v, kTileCapElems));
+        const int NF = class_nf(c);
+        int X = 0;
+        while (X + 1 < kNumPairClass && quartet_class(X + 1, 0) <= c) ++X;
+        const int Y = c - quartet_class(X, 0);
+        const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
+        const int NA = ncart(la), NB = ncart(lb);
+        for (int tier = 0; tier < (mixed ? 2 : 1); ++tier) {
+            const int fp32 = mixed && tier == 1;
+            LaunchRec L;
+            L.cls = c;
+            L.fp32 = fp32;
+            long long used = 0;
+            auto flush = [&]() {
+                if (L.neri > 0) {
+                    int kmax = 0;
+                    for (int x = 0; x < 8; ++x) kmax = std::max(kmax, L.kcount[x]);
+                    L.dig_blocks = static_cast<unsigned>(8 * kmax);
+                    wp.launches.push_back(L);
+                }
+                LaunchRec fresh;
+                fresh.cls = c;
+                fresh.fp32 = fp32;
+                fresh.eri0 = static_cast<int>(wp.eri.size());
+                fresh.dig0 = static_cast<int>(wp.dig.size());
+                L = fresh;
+                used = 0;
+            };
+            flush();
+            for (size_t mi = 0; mi < mols.size(); ++mi) {
+                jk_basis_s* h = mols[mi].h;
+                const int nd = mols[mi].nd;
+                const ClassList& CL = h->lists[c];
+                if (CL.count == 0) continue;
+                const int nseg = static_cast<int>(CL.segs.size());
+                const int sbeg = tier ? CL.nseg64 : 0, send = (tier || !mixed) ? nseg : CL.nseg64;
+                if (sbeg >= send) continue;
+                const long long nq_tier = mixed ? (tier ? CL.count - CL.n64 : CL.n64) : CL.count;
+                const double prim_tier = mixed ? CL.prim_quartets[tier] : CL.prim_quartets[0] + CL.prim_quartets[1];
+                const double prim_avg = prim_tier / static_cast<double>(std::max<long long>(nq_tier, 1));
+                const int colA0 = h->lw_off[lc], colAw = h->lw_len[lc];
+                const int colB0 = ld != lc ? h->lw_off[ld] : 0, colBw = ld != lc ? h->lw_len[ld] : 0;
+                const size_t per_density = sizeof(double) * ((o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0) +
+                                                             (o->want_j ? NA * NB : 0));
+                if (per_density > static_cast<size_t>(lds_cap))
+                    return fail(JK_EUNSUPPORTED, "class %d of a %d-function basis needs %zu bytes of LDS per density "
+                                "(limit %d)", c, h->nc, per_density, lds_cap);
+                int G = 16;
+                const int gmax = tune_of(c).g_max;
+                while (G > 1 && (G > gmax || G / 2 >= nd || G * per_density > static_cast<size_t>(lds_cap))) G /= 2;
+                const int ngroups = (nd + G - 1) / G;
+                for (int s0 = sbeg; s0 < send;) {
+                    const long long q0 = CL.segs[s0].x;
+                    int s1 = s0;
+                    while (s1 < send && (CL.segs[s1].x + CL.segs[s1].y - q0) * NF <= cap - used) ++s1;
+                    if (s1 == s0) {
+                        if (used > 0) {
+                            flush();
+                            continue;
+                        }
+                        return fail(JK_EDEVICE, "internal: a segment exceeds the work buffer");
+                    }
+                    const long long n = CL.segs[s1 - 1].x + CL.segs[s1 - 1].y - q0;
+                    EriItem e{};
+                    e.quartets = CL.dev + q0;
+                    e.n = n;
+                    e.tile_off = used;
+                    e.blk0 = L.eri_blocks;
+                    e.mol = static_cast<int>(mi);
+                    wp.eri.push_back(e);
+                    L.neri++;
+                    L.eri_blocks += (n + 255) / 256;
+                    for (int k = s0; k < s1; ++k) {
+                        DigItem d{};
+                        d.quartets = CL.dev;
+                        d.seg = CL.segs[k];
+                        d.chunk_q0 = q0;
+                        d.chunk_n = n;
+                        d.tile_off = used;
+                        d.mol = static_cast<int>(mi);
+                        d.G = G;
+                        d.ngroups = ngroups;
+                        const int x = L.ndig % 8;
+                        d.kstart = L.kcount[x];
+                        L.kcount[x] += ngroups;
+                        d.colA0 = colA0;
+                        d.colAw = colAw;
+                        d.colB0 = colB0;
+                        d.colBw = colBw;
+                        wp.dig.push_back(d);
+                        L.ndig++;
+                    }
+                    L.lds = std::max(L.lds, G * per_density);
+                    const double ef = n * (prim_avg * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
+                                           kClassCost[c].hrr_flops);
+                    const double df = static_cast<double>(n) * NF * nd *
+                                      (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0));
+                    L.eri_flops += ef;
+                    L.dig_flops += df;
+                    L.quartets += n;
+                    L.tile_bytes += static_cast<double>(n) * NF * (fp32 ? sizeof(float) : sizeof(double));
+                    wp.stats[0] += n;
+                    if (fp32) wp.stats[1] += n;
+                    wp.stats[2] += static_cast<double>(n) * NF;
+                    wp.stats[3] += n * prim_avg;
+                    wp.stats[4] += ef;
+                    wp.stats[5] += df;
+                    used += n * NF;
+                    wp.tile_elems = std::max(wp.tile_elems, used);
+                    s0 = s1;
+                }
+            }
+            flush();
+        }
     }
-    if (h->list_tol < 0) need = kTileCapElems;
-    p.tile_elems = need;
-    p.off_tile = off;
-    off += al(static_cast<size_t>(need) * sizeof(double));
-    p.off_scr = off;   // (e0|cd) of pass-evaluated classes: never larger than the tile
-    off += al(static_cast<size_t>(need) * sizeof(double));
-    p.total = off;
-    return p;
+    return JK_OK;
 }
+
+// Per-molecule workspace: densities and accumulators.
+struct MolSpace {
+    size_t off_D, off_J, off_K, off_KT, off_dmax, bytes;
+};
+
+inline size_t al256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
+    MolSpace m{};
+    const size_t mat = static_cast<size_t>(h->nc) * h->nc * nd * sizeof(double);
+    size_t off = 0;
+    m.off_D = off;
+    off += al256(mat);
+    m.off_J = off;
+    if (o->want_j) off += al256(mat);
+    m.off_K = off;
+    if (o->want_k) off += al256(mat);
+    m.off_KT = off;
+    if (o->want_k) off += al256(mat);
+    m.off_dmax = off;
+    off += al256(static_cast<size_t>(h->ns) * h->ns * sizeof(double));
+    m.bytes = off;
+    return m;
+}
+
+// A cached plan of a single-molecule build, with its items on the device.
+struct CachedPlan {
+    int nd, mixed, want_j, want_k, gen;
+    WorkPlan wp;
+    EriItem* d_eri = nullptr;
+    DigItem* d_dig = nullptr;
+};
 
 bool valid_opts(const jk_build_opts* o) {
     return o && (o->precision == JK_FP64 || o->precision == JK_MIXED) && std::isfinite(o->schwarz_tol) &&
@@ -587,20 +792,29 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     if ((rc = upload(&h->d_pairs, h->pairs))) return rc;
     if ((rc = upload(&h->d_prims, h->prims))) return rc;
     if ((rc = upload(&h->d_boys, boys_table()))) return rc;
+    {
+        std::vector<float> t32(boys_table().begin(), boys_table().end());
+        if ((rc = upload(&h->d_boys32, t32))) return rc;
+    }
     if ((rc = upload(&h->d_cmap, cmap))) return rc;
     if ((rc = upload(&h->d_umap, umap))) return rc;
     if ((rc = upload(&h->d_shell_f0, sf0))) return rc;
     if ((rc = upload(&h->d_shell_nf, h->ncart_int))) return rc;
     if ((rc = compute_schwarz(h.get()))) return rc;
     HIPC(hipMemcpy(h->d_pairs, h->pairs.data(), h->pairs.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
-    if ((rc = ensure_lists(h.get(), 1e-12))) return rc;
+    if ((rc = ensure_lists(h.get(), 1e-12, 1e-6))) return rc;
     *out = h.release();
     return JK_OK;
 }
 
 int jk_nbf(jk_basis_t h) { return h ? h->nf : fail(JK_EINVAL, "jk_nbf: NULL handle"); }
 
-void jk_destroy(jk_basis_t h) { delete h; }
+void jk_destroy(jk_basis_t h) {
+    if (!h) return;
+    for (CachedPlan* cp : h->plans) free_plan(cp);
+    h->plans.clear();
+    delete h;
+}
 
 int64_t jk_quartet_count(jk_basis_t h, double tol) {
     if (!h || !(tol >= 0)) return fail(JK_EINVAL, "jk_quartet_count: bad arguments");
@@ -615,22 +829,190 @@ int64_t jk_quartet_count(jk_basis_t h, double tol) {
     return n;
 }
 
+int jk_last_stats(jk_basis_t h, double out[6]) {
+    if (!h || !out) return fail(JK_EINVAL, "jk_last_stats: bad arguments");
+    std::lock_guard<std::mutex> g(h->mu);
+    for (int i = 0; i < 6; ++i) out[i] = h->stats[i];
+    return JK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::mutex g_prep_mu;
+size_t g_prepared[kNumClass] = {};   // dynamic LDS granted per digestion kernel
+
+hipError_t prepare_lds(int cls, size_t bytes) {
+    std::lock_guard<std::mutex> g(g_prep_mu);
+    if (g_prepared[cls] >= bytes) return hipSuccess;
+    hipError_t e = digest_prepare(cls, bytes);
+    if (e == hipSuccess) g_prepared[cls] = bytes;
+    return e;
+}
+
+// Launch every class/tier of a plan on stream s.  prof: handle that records
+// per-kernel events when profiling is on (single-molecule builds).
+hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, const DigItem* d_dig, const MolDesc& mol0,
+                    const MolDesc* d_mols, void* tiles, void* scratch, const jk_build_opts* o, const double* boys,
+                    const float* boys32, hipStream_t s, jk_basis_s* prof) {
+    hipError_t e = hipSuccess;
+    for (const LaunchRec& L : wp.launches) {
+        e = prepare_lds(L.cls, L.lds);
+        if (e != hipSuccess) return e;
+        EriTileArgs ea{};
+        ea.items = d_eri + L.eri0;
+        ea.nitems = L.neri;
+        ea.nblocks = L.eri_blocks;
+        ea.mol0 = mol0;
+        ea.mols = d_mols;
+        ea.boys = boys;
+        ea.boys32 = boys32;
+        ea.tol = o->schwarz_tol;
+        ea.tiles = tiles;
+        ea.scratch = scratch;
+        DigestArgs da{};
+        da.items = d_dig + L.dig0;
+        da.nitems = L.ndig;
+        da.mol0 = mol0;
+        da.mols = d_mols;
+        da.tol = o->schwarz_tol;
+        da.tiles = tiles;
+        da.want_j = o->want_j;
+        da.want_k = o->want_k;
+        da.lds_bytes = L.lds;
+        da.nblocks = L.dig_blocks;
+        const bool timed = prof && prof->profiling;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (timed) {
+            for (auto& x : ev)
+                if (e == hipSuccess) e = hipEventCreate(&x);
+            if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_eri_tile(L.cls, ea, s, L.fp32);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = launch_digest(L.cls, da, s, L.fp32);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[2], s);
+        if (e != hipSuccess) return e;
+        if (timed) {
+            std::lock_guard<std::mutex> g(prof->mu);
+            prof->prof.push_back({0 + 2 * L.fp32, L.cls, ev[0], ev[1], L.eri_flops, L.quartets, L.tile_bytes});
+            prof->prof.push_back({1 + 2 * L.fp32, L.cls, ev[1], ev[2], L.dig_flops, L.quartets, L.tile_bytes});
+        }
+    }
+    return e;
+}
+
+void free_plan(CachedPlan* cp) {
+    if (!cp) return;
+    (void)hipFree(cp->d_eri);
+    (void)hipFree(cp->d_dig);
+    delete cp;
+}
+
+// The cached plan of a single-molecule build (created on first use).
+int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
+    const int mixed = o->precision == JK_MIXED;
+    std::lock_guard<std::mutex> g(h->mu);
+    for (CachedPlan* cp : h->plans)
+        if (cp->nd == nd && cp->mixed == mixed && cp->want_j == o->want_j && cp->want_k == o->want_k &&
+            cp->gen == h->list_gen) {
+            *out = cp;
+            return JK_OK;
+        }
+    CachedPlan* cp = new CachedPlan();
+    cp->nd = nd;
+    cp->mixed = mixed;
+    cp->want_j = o->want_j;
+    cp->want_k = o->want_k;
+    cp->gen = h->list_gen;
+    int rc = plan_work({MolRun{h, nd}}, o, h->lds_cap, kTileCapElems, cp->wp);
+    if (!rc) rc = upload(&cp->d_eri, cp->wp.eri);
+    if (!rc) rc = upload(&cp->d_dig, cp->wp.dig);
+    if (rc) {
+        free_plan(cp);
+        return rc;
+    }
+    h->plans.push_back(cp);
+    *out = cp;
+    return JK_OK;
+}
+
+// Pre- and post-stages of one molecule: D_cart, density screen, zeroed
+// accumulators; back-transform of J and K.
+hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_opts* o, char* base,
+                   const MolSpace& ms, MolDesc& md, hipStream_t s) {
+    double* Dc = reinterpret_cast<double*>(base + ms.off_D);
+    double* Jc = o->want_j ? reinterpret_cast<double*>(base + ms.off_J) : nullptr;
+    double* Kc = o->want_k ? reinterpret_cast<double*>(base + ms.off_K) : nullptr;
+    double* KTc = o->want_k ? reinterpret_cast<double*>(base + ms.off_KT) : nullptr;
+    double* dmax = reinterpret_cast<double*>(base + ms.off_dmax);
+    const long long mat = static_cast<long long>(h->nc) * h->nc * nd;
+    hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, nd, Dc, s);
+    if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, nd, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
+    if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
+    if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
+    if (e == hipSuccess && KTc) e = launch_zero(KTc, mat, s);
+    md.pairs = h->d_pairs;
+    md.prims = h->d_prims;
+    md.dmax = dmax;
+    md.D = Dc;
+    md.J = Jc;
+    md.K = Kc;
+    md.KT = KTc;
+    md.ns = h->ns;
+    md.nc = h->nc;
+    md.nd = nd;
+    return e;
+}
+
+hipError_t mol_post(const jk_basis_s* h, int nd, const MolDesc& md, double* J, double* K, hipStream_t s) {
+    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, nd, J, K, s);
+}
+
+int check_opts(const char* who, const jk_build_opts* o) {
+    if (!valid_opts(o)) return fail(JK_EINVAL, "%s: invalid options", who);
+    if (o->precision == JK_MIXED && !(o->fp32_bound >= 0 && std::isfinite(o->fp32_bound)))
+        return fail(JK_EINVAL, "%s: fp32_bound must be finite and >= 0", who);
+    return JK_OK;
+}
+
+size_t tile_bytes_of(const WorkPlan& wp) { return al256(static_cast<size_t>(wp.tile_elems) * sizeof(double)); }
+
+struct DeviceGuard {
+    int prev = -1;
+    int ok(int dev) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return fail(JK_EDEVICE, "hipGetDevice failed");
+        if (cur != dev) {
+            if (hipSetDevice(dev) != hipSuccess) return fail(JK_EDEVICE, "hipSetDevice(%d) failed", dev);
+            prev = cur;
+        }
+        return JK_OK;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
 size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o) {
     jk_build_opts def;
     if (!o) {
         jk_default_opts(&def);
         o = &def;
     }
-    if (!h || nd < 1 || !valid_opts(o)) return 0;
-    if (ensure_lists(h, o->schwarz_tol)) return 0;
-    return make_plan(h, nd, o).total;
-}
-
-int jk_last_stats(jk_basis_t h, double out[6]) {
-    if (!h || !out) return fail(JK_EINVAL, "jk_last_stats: bad arguments");
-    std::lock_guard<std::mutex> g(h->mu);
-    for (int i = 0; i < 6; ++i) out[i] = h->stats[i];
-    return JK_OK;
+    if (!h || nd < 1 || check_opts("jk_workspace_bytes", o)) return 0;
+    DeviceGuard dg;
+    if (dg.ok(h->device)) return 0;
+    if (ensure_lists(h, o->schwarz_tol, o->precision == JK_MIXED ? o->fp32_bound : -1.0)) return 0;
+    CachedPlan* cp = nullptr;
+    if (get_plan(h, nd, o, &cp)) return 0;
+    return mol_space(h, nd, o).bytes + 2 * tile_bytes_of(cp->wp);
 }
 
 int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o) {
@@ -641,171 +1023,42 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     }
     if (!h) return fail(JK_EINVAL, "jk_build: NULL handle");
     if (nd < 1) return fail(JK_EINVAL, "jk_build: nd=%d must be >= 1", nd);
-    if (!valid_opts(o)) return fail(JK_EINVAL, "jk_build: invalid options");
+    int rc = check_opts("jk_build", o);
+    if (rc) return rc;
     if (!D) return fail(JK_EINVAL, "jk_build: D is NULL");
     if (o->want_j && !J) return fail(JK_EINVAL, "jk_build: J is NULL but want_j is set");
     if (o->want_k && !K) return fail(JK_EINVAL, "jk_build: K is NULL but want_k is set");
-    if (o->precision != JK_FP64) return fail(JK_EUNSUPPORTED, "jk_build: only JK_FP64 is available in this build");
-    int cur = 0;
-    HIPC(hipGetDevice(&cur));
-    if (cur != h->device) HIPC(hipSetDevice(h->device));
-    int rc = ensure_lists(h, o->schwarz_tol);
-    if (rc) return rc;
+    DeviceGuard dg;
+    if ((rc = dg.ok(h->device))) return rc;
+    const int mixed = o->precision == JK_MIXED;
+    if ((rc = ensure_lists(h, o->schwarz_tol, mixed ? o->fp32_bound : -1.0))) return rc;
+    CachedPlan* cp = nullptr;
+    if ((rc = get_plan(h, nd, o, &cp))) return rc;
     hipStream_t s = static_cast<hipStream_t>(o->stream);
-    const Plan p = make_plan(h, nd, o);
+    const MolSpace ms = mol_space(h, nd, o);
+    const size_t tb = tile_bytes_of(cp->wp);
+    const size_t total = ms.bytes + 2 * tb;
     char* ws = static_cast<char*>(o->workspace);
     bool own = false;
     if (ws) {
-        if (o->workspace_bytes < p.total)
+        if (o->workspace_bytes < total)
             return fail(JK_EINVAL, "jk_build: workspace of %zu bytes is below the %zu required", o->workspace_bytes,
-                        p.total);
+                        total);
     } else {
-        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), p.total, s);
+        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), total, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return fail(JK_ENOMEM, "jk_build: cannot allocate %zu bytes of workspace (%s)", p.total,
+            return fail(JK_ENOMEM, "jk_build: cannot allocate %zu bytes of workspace (%s)", total,
                         hipGetErrorString(e));
         }
         own = true;
     }
-    double* Dc = reinterpret_cast<double*>(ws + p.off_D);
-    double* Jc = o->want_j ? reinterpret_cast<double*>(ws + p.off_J) : nullptr;
-    double* Kc = o->want_k ? reinterpret_cast<double*>(ws + p.off_K) : nullptr;
-    double* KTc = o->want_k ? reinterpret_cast<double*>(ws + p.off_KT) : nullptr;
-    double* dmax = reinterpret_cast<double*>(ws + p.off_dmax);
-    double* tiles = reinterpret_cast<double*>(ws + p.off_tile);
-    double* scratch = reinterpret_cast<double*>(ws + p.off_scr);
-    const long long mat = static_cast<long long>(h->nc) * h->nc * p.ndp;
-    const long long kmat = static_cast<long long>(h->nc) * h->nc * nd;
-    hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, p.ndp, Dc, s);
-    if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, p.ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
-    if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
-    if (e == hipSuccess && Kc) e = launch_zero(Kc, kmat, s);
-    if (e == hipSuccess && KTc) e = launch_zero(KTc, kmat, s);
-    double nq_tot = 0, nfq = 0, npq = 0, eri_flops = 0, dig_flops = 0;
-    for (int c = 0; c < kNumClass && e == hipSuccess; ++c) {
-        const ClassList& L = h->lists[c];
-        if (L.count == 0) continue;
-        const int NF = class_nf(c);
-        int X = 0;
-        while (quartet_class(X + 1, 0) <= c && X + 1 < kNumPairClass) ++X;
-        const int Y = c - quartet_class(X, 0);
-        const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
-        const int NA = ncart(la), NB = ncart(lb);
-        // LDS windows: Cartesian functions of the ket shells' angular momenta
-        const int colA0 = h->lw_off[lc], colAw = h->lw_len[lc];
-        const int colB0 = ld != lc ? h->lw_off[ld] : 0, colBw = ld != lc ? h->lw_len[ld] : 0;
-        const size_t per_density = sizeof(double) * ((o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0) +
-                                                     (o->want_j ? NA * NB : 0));
-        int G = 16;
-        while (G > 1 && (G / 2 >= nd || G * per_density > static_cast<size_t>(h->lds_cap))) G /= 2;
-        if (per_density > static_cast<size_t>(h->lds_cap)) {
-            if (own) (void)hipFreeAsync(ws, s);
-            return fail(JK_EUNSUPPORTED, "jk_build: class %d needs %zu bytes of LDS per density (limit %d)", c,
-                        per_density, h->lds_cap);
-        }
-        const size_t lds_bytes = G * per_density;
-        {
-            std::lock_guard<std::mutex> g(h->mu);
-            if (h->prepared[c] < lds_bytes) {
-                e = digest_prepare(c, lds_bytes);
-                if (e == hipSuccess) h->prepared[c] = lds_bytes;
-            }
-        }
-        if (e != hipSuccess) break;
-        const long long cap = p.tile_elems / NF;
-        const int nseg = static_cast<int>(L.segs.size());
-        for (int s0 = 0; s0 < nseg && e == hipSuccess;) {
-            // chunk: whole segments whose quartets fit the tile buffer
-            const long long q0 = L.segs[s0].x;
-            int s1 = s0;
-            while (s1 < nseg && L.segs[s1].x + L.segs[s1].y - q0 <= cap) ++s1;
-            if (s1 == s0) {
-                e = hipErrorInvalidValue;   // a segment larger than the work buffer: never by construction
-                break;
-            }
-            const long long q1 = L.segs[s1 - 1].x + L.segs[s1 - 1].y;
-            const long long n = q1 - q0;
-            EriTileArgs ea{};
-            ea.quartets = L.dev + q0;
-            ea.nq = n;
-            ea.pairs = h->d_pairs;
-            ea.prims = h->d_prims;
-            ea.boys = h->d_boys;
-            ea.dmax = dmax;
-            ea.ns = h->ns;
-            ea.tol = o->schwarz_tol;
-            ea.out = tiles;
-            ea.scratch = scratch;
-            const double cost_q = L.prim_quartets / static_cast<double>(L.count);
-            hipEvent_t ev[2] = {nullptr, nullptr};
-            if (h->profiling) {
-                for (auto& x : ev)
-                    if (e == hipSuccess) e = hipEventCreate(&x);
-                if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-                if (e != hipSuccess) break;
-            }
-            e = launch_eri_tile(c, ea, s);
-            if (e != hipSuccess) break;
-            if (h->profiling) {
-                e = hipEventRecord(ev[1], s);
-                if (e != hipSuccess) break;
-                std::lock_guard<std::mutex> g(h->mu);
-                h->prof.push_back({0, c, ev[0], ev[1],
-                                   n * (cost_q * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
-                                        kClassCost[c].hrr_flops),
-                                   static_cast<double>(n), static_cast<double>(n) * NF * sizeof(double)});
-            }
-            DigestArgs da{};
-            da.quartets = L.dev + q0;
-            da.nq = n;
-            da.segs = L.dev_segs + s0;
-            da.qbase = q0;
-            da.nseg = s1 - s0;
-            da.G = G;
-            da.ngroups = (nd + G - 1) / G;
-            da.nd = nd;
-            da.pairs = h->d_pairs;
-            da.dmax = dmax;
-            da.ns = h->ns;
-            da.tol = o->schwarz_tol;
-            da.tiles = tiles;
-            da.D = Dc;
-            da.J = Jc;
-            da.K = Kc;
-            da.KT = KTc;
-            da.nc = h->nc;
-            da.ndp = p.ndp;
-            da.colA0 = colA0;
-            da.colAw = colAw;
-            da.colB0 = colB0;
-            da.colBw = colBw;
-            da.want_j = o->want_j;
-            da.want_k = o->want_k;
-            e = launch_digest(c, da, s);
-            if (h->profiling && e == hipSuccess) {
-                hipEvent_t e2 = nullptr;
-                e = hipEventCreate(&e2);
-                if (e == hipSuccess) e = hipEventRecord(e2, s);
-                if (e == hipSuccess) {
-                    std::lock_guard<std::mutex> g(h->mu);
-                    h->prof.push_back({1, c, ev[1], e2,
-                                       static_cast<double>(n) * NF * nd *
-                                           (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0)),
-                                       static_cast<double>(n),
-                                       static_cast<double>(n) * NF * sizeof(double) * da.ngroups});
-                }
-            }
-            s0 = s1;
-        }
-        nq_tot += L.count;
-        nfq += static_cast<double>(L.count) * NF;
-        npq += L.prim_quartets;
-        eri_flops += L.prim_quartets * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
-                     static_cast<double>(L.count) * kClassCost[c].hrr_flops;
-        dig_flops += static_cast<double>(L.count) * NF * nd * (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0));
-    }
-    if (e == hipSuccess) e = launch_cart2sph(Jc, Kc, KTc, nd, h->nf, h->d_umap, h->nc, p.ndp, J, K, s);
+    MolDesc md{};
+    hipError_t e = mol_pre(h, nd, D, o, ws, ms, md, s);
+    if (e == hipSuccess)
+        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, ws + ms.bytes + tb, o, h->d_boys,
+                     h->d_boys32, s, h);
+    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, s);
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (e == hipSuccess) e = e2;
@@ -813,15 +1066,320 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     if (e != hipSuccess) return fail(JK_EDEVICE, "jk_build: %s", hipGetErrorString(e));
     {
         std::lock_guard<std::mutex> g(h->mu);
-        h->stats[0] = nq_tot;
-        h->stats[1] = 0;
-        h->stats[2] = nfq;
-        h->stats[3] = npq;
-        h->stats[4] = eri_flops;
-        h->stats[5] = dig_flops;
+        for (int i = 0; i < 6; ++i) h->stats[i] = cp->wp.stats[i];
     }
-    if (cur != h->device) (void)hipSetDevice(cur);
     return JK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host memory released by the stream once the work before it has run.
+void free_host_cb(void* p) { std::free(p); }
+
+struct BatchSetup {
+    std::vector<MolRun> runs;
+    WorkPlan wp;
+    std::vector<MolSpace> ms;
+    std::vector<size_t> mol_off;
+    size_t off_tiles = 0, off_scr = 0, off_items = 0, total = 0;
+    size_t eri_bytes = 0, dig_bytes = 0, mol_bytes = 0;
+};
+
+int batch_setup(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const jk_build_opts* o, BatchSetup& b) {
+    if (nmol < 1 || !hs || !nd) return fail(JK_EINVAL, "jk_build_batch: nmol >= 1 and non-NULL arrays required");
+    const int mixed = o->precision == JK_MIXED;
+    int lds_cap = 1 << 30;
+    for (int i = 0; i < nmol; ++i) {
+        if (!hs[i]) return fail(JK_EINVAL, "jk_build_batch: handle %d is NULL", i);
+        if (nd[i] < 1) return fail(JK_EINVAL, "jk_build_batch: nd[%d]=%d must be >= 1", i, nd[i]);
+        if (hs[i]->device != hs[0]->device) return fail(JK_EINVAL, "jk_build_batch: handles on different devices");
+        int rc = ensure_lists(hs[i], o->schwarz_tol, mixed ? o->fp32_bound : -1.0);
+        if (rc) return rc;
+        lds_cap = std::min(lds_cap, hs[i]->lds_cap);
+        b.runs.push_back(MolRun{hs[i], nd[i]});
+    }
+    int rc = plan_work(b.runs, o, lds_cap, kTileCapElems, b.wp);
+    if (rc) return rc;
+    size_t off = 0;
+    for (int i = 0; i < nmol; ++i) {
+        b.ms.push_back(mol_space(hs[i], nd[i], o));
+        b.mol_off.push_back(off);
+        off += b.ms.back().bytes;
+    }
+    const size_t tb = tile_bytes_of(b.wp);
+    b.off_tiles = off;
+    off += tb;
+    b.off_scr = off;
+    off += tb;
+    b.off_items = off;
+    b.eri_bytes = al256(std::max<size_t>(1, b.wp.eri.size()) * sizeof(EriItem));
+    b.dig_bytes = al256(std::max<size_t>(1, b.wp.dig.size()) * sizeof(DigItem));
+    b.mol_bytes = al256(nmol * sizeof(MolDesc));
+    off += b.eri_bytes + b.dig_bytes + b.mol_bytes;
+    b.total = off;
+    return JK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t* nd, const jk_build_opts* o) {
+    jk_build_opts def;
+    if (!o) {
+        jk_default_opts(&def);
+        o = &def;
+    }
+    if (check_opts("jk_batch_workspace_bytes", o) || nmol < 1 || !h || !h[0]) return 0;
+    DeviceGuard dg;
+    if (dg.ok(h[0]->device)) return 0;
+    BatchSetup b;
+    if (batch_setup(nmol, h, nd, o, b)) return 0;
+    return b.total;
+}
+
+int jk_build_batch(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const double* const* D,
+                   double* const* J, double* const* K, const jk_build_opts* o) {
+    jk_build_opts def;
+    if (!o) {
+        jk_default_opts(&def);
+        o = &def;
+    }
+    int rc = check_opts("jk_build_batch", o);
+    if (rc) return rc;
+    if (nmol < 1 || !hs || !nd || !D || (o->want_j && !J) || (o->want_k && !K))
+        return fail(JK_EINVAL, "jk_build_batch: NULL arrays");
+    for (int i = 0; i < nmol; ++i)
+        if (!D[i] || (o->want_j && !J[i]) || (o->want_k && !K[i]))
+            return fail(JK_EINVAL, "jk_build_batch: NULL matrix pointer for molecule %d", i);
+    if (!hs[0]) return fail(JK_EINVAL, "jk_build_batch: handle 0 is NULL");
+    DeviceGuard dg;
+    if ((rc = dg.ok(hs[0]->device))) return rc;
+    BatchSetup b;
+    if ((rc = batch_setup(nmol, hs, nd, o, b))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(o->stream);
+    char* ws = static_cast<char*>(o->workspace);
+    bool own = false;
+    if (ws) {
+        if (o->workspace_bytes < b.total)
+            return fail(JK_EINVAL, "jk_build_batch: workspace of %zu bytes is below the %zu required",
+                        o->workspace_bytes, b.total);
+    } else {
+        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws), b.total, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(JK_ENOMEM, "jk_build_batch: cannot allocate %zu bytes of workspace (%s)", b.total,
+                        hipGetErrorString(e));
+        }
+        own = true;
+    }
+    std::vector<MolDesc> mds(nmol);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nmol && e == hipSuccess; ++i)
+        e = mol_pre(hs[i], nd[i], D[i], o, ws + b.mol_off[i], b.ms[i], mds[i], s);
+    // work items and molecule table, staged through host memory the stream frees
+    EriItem* d_eri = reinterpret_cast<EriItem*>(ws + b.off_items);
+    DigItem* d_dig = reinterpret_cast<DigItem*>(ws + b.off_items + b.eri_bytes);
+    MolDesc* d_mols = reinterpret_cast<MolDesc*>(ws + b.off_items + b.eri_bytes + b.dig_bytes);
+    const size_t host_bytes = b.eri_bytes + b.dig_bytes + b.mol_bytes;
+    char* stage = static_cast<char*>(std::malloc(host_bytes));
+    if (!stage) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) {
+        std::memcpy(stage, b.wp.eri.data(), b.wp.eri.size() * sizeof(EriItem));
+        std::memcpy(stage + b.eri_bytes, b.wp.dig.data(), b.wp.dig.size() * sizeof(DigItem));
+        std::memcpy(stage + b.eri_bytes + b.dig_bytes, mds.data(), nmol * sizeof(MolDesc));
+        e = hipMemcpyAsync(ws + b.off_items, stage, host_bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipLaunchHostFunc(s, free_host_cb, stage);
+        else std::free(stage);
+    }
+    if (e == hipSuccess)
+        e = run_plan(b.wp, d_eri, d_dig, mds[0], d_mols, ws + b.off_tiles, ws + b.off_scr, o, hs[0]->d_boys,
+                     hs[0]->d_boys32, s, nullptr);
+    for (int i = 0; i < nmol && e == hipSuccess; ++i)
+        e = mol_post(hs[i], nd[i], mds[i], o->want_j ? J[i] : nullptr, o->want_k ? K[i] : nullptr, s);
+    if (own) {
+        hipError_t e2 = hipFreeAsync(ws, s);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return fail(JK_EDEVICE, "jk_build_batch: %s", hipGetErrorString(e));
+    for (int i = 0; i < nmol; ++i) {
+        std::lock_guard<std::mutex> g(hs[i]->mu);
+        hs[i]->stats[0] = -1;   // per-molecule statistics are not kept for batches
+    }
+    return JK_OK;
+}
+
+int jk_tune_set(int32_t cls, int32_t seg_max, int32_t g_max) {
+    if (cls < 0 || cls >= kNumClass || seg_max < 1 || seg_max > (1 << 20) || !(g_max == 1 || g_max == 2 ||
+        g_max == 4 || g_max == 8 || g_max == 16))
+        return fail(JK_EINVAL, "jk_tune_set: bad arguments");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[cls].seg_max = seg_max;
+    g_tune[cls].g_max = g_max;
+    ++g_tune_gen;
+    return JK_OK;
+}
+
+int jk_tune_get(int32_t cls, int32_t* seg_max, int32_t* g_max) {
+    if (cls < 0 || cls >= kNumClass || !seg_max || !g_max) return fail(JK_EINVAL, "jk_tune_get: bad arguments");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    *seg_max = g_tune[cls].seg_max;
+    *g_max = g_tune[cls].g_max;
+    return JK_OK;
+}
+
+static const char* kArch = "gfx950";
+
+int jk_tune_load(const char* path) {
+    if (!path) return fail(JK_EINVAL, "jk_tune_load: NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(JK_EINVAL, "jk_tune_load: cannot open %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+    std::fclose(f);
+    if (txt.find(std::string("\"arch\": \"") + kArch + "\"") == std::string::npos)
+        return fail(JK_EUNSUPPORTED, "jk_tune_load: %s holds no entries for %s", path, kArch);
+    int applied = 0;
+    size_t pos = 0;
+    while ((pos = txt.find("\"class\":", pos)) != std::string::npos) {
+        int cls = -1, seg = 0, gm = 0;
+        const size_t end = txt.find('}', pos);
+        const std::string ent = txt.substr(pos, end - pos);
+        if (std::sscanf(ent.c_str(), "\"class\": %d", &cls) == 1) {
+            const size_t ps = ent.find("\"seg_max\":"), pg = ent.find("\"g_max\":");
+            if (ps != std::string::npos && pg != std::string::npos &&
+                std::sscanf(ent.c_str() + ps, "\"seg_max\": %d", &seg) == 1 &&
+                std::sscanf(ent.c_str() + pg, "\"g_max\": %d", &gm) == 1 && jk_tune_set(cls, seg, gm) == JK_OK)
+                ++applied;
+        }
+        pos = end == std::string::npos ? txt.size() : end;
+    }
+    return applied > 0 ? JK_OK : fail(JK_EINVAL, "jk_tune_load: no valid entries in %s", path);
+}
+
+int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o,
+                const char* cache_path) {
+    if (!h || !o || nd < 1 || !D || !J || !K) return fail(JK_EINVAL, "jk_autotune: bad arguments");
+    static const int kSeg[] = {128, 256, 512, 1024, 2048};
+    static const int kG[] = {4, 8, 16};
+    double best_ms[kNumClass];
+    Tune best[kNumClass];
+    for (int c = 0; c < kNumClass; ++c) best_ms[c] = 1e300;
+    jk_build_opts oo = *o;
+    hipStream_t s = static_cast<hipStream_t>(o->stream);
+    for (int si : kSeg)
+        for (int gi : kG) {
+            for (int c = 0; c < kNumClass; ++c) {
+                int rc = jk_tune_set(c, si, gi);
+                if (rc) return rc;
+            }
+            int rc = jk_build(h, nd, D, J, K, &oo);   // warm-up: lists, plans
+            if (rc) return rc;
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(JK_EDEVICE, "jk_autotune: sync failed");
+            jk_profile_enable(h, 1);
+            for (int r = 0; r < 2 && !rc; ++r) rc = jk_build(h, nd, D, J, K, &oo);
+            jk_profile_enable(h, 0);
+            if (rc) return rc;
+            for (int c = 0; c < kNumClass; ++c) {
+                double tot = 0, v[5];
+                for (int kind = 0; kind < 4; ++kind) {
+                    if ((rc = jk_profile_read(h, kind, c, v))) return rc;
+                    tot += v[0];
+                }
+                if (tot > 0 && tot < best_ms[c]) {
+                    best_ms[c] = tot;
+                    best[c].seg_max = si;
+                    best[c].g_max = gi;
+                }
+            }
+        }
+    for (int c = 0; c < kNumClass; ++c) jk_tune_set(c, best[c].seg_max, best[c].g_max);
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "w");
+        if (!f) return fail(JK_EINVAL, "jk_autotune: cannot write %s", cache_path);
+        std::fprintf(f, "{\"arch\": \"%s\", \"nd\": %d, \"nbf\": %d, \"entries\": [\n", kArch, nd, h->nf);
+        for (int c = 0; c < kNumClass; ++c)
+            std::fprintf(f, "  {\"class\": %d, \"seg_max\": %d, \"g_max\": %d, \"ms_per_build\": %.5f}%s\n", c,
+                         best[c].seg_max, best[c].g_max, best_ms[c] < 1e299 ? best_ms[c] / 2 : -1.0,
+                         c + 1 < kNumClass ? "," : "");
+        std::fprintf(f, "]}\n");
+        std::fclose(f);
+    }
+    return JK_OK;
+}
+
+struct jk_graph_s {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int jk_graph_create(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o,
+                    jk_graph_t* out) {
+    if (!out) return fail(JK_EINVAL, "jk_graph_create: out is NULL");
+    *out = nullptr;
+    if (!h || !o) return fail(JK_EINVAL, "jk_graph_create: NULL handle or options");
+    if (!o->workspace) return fail(JK_EINVAL, "jk_graph_create: a workspace is required");
+    if (h->profiling) return fail(JK_EINVAL, "jk_graph_create: profiling must be off");
+    DeviceGuard dg;
+    int rc = dg.ok(h->device);
+    if (rc) return rc;
+    // plan and kernel attributes outside the capture
+    if (jk_workspace_bytes(h, nd, o) == 0) return fail(JK_EINVAL, "jk_graph_create: invalid build arguments");
+    {
+        CachedPlan* cp = nullptr;
+        if ((rc = get_plan(h, nd, o, &cp))) return rc;
+        for (const LaunchRec& L : cp->wp.launches)
+            if (prepare_lds(L.cls, L.lds) != hipSuccess) return fail(JK_EDEVICE, "jk_graph_create: LDS attribute");
+    }
+    hipStream_t cs = nullptr;
+    HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    jk_build_opts oc = *o;
+    oc.stream = cs;
+    std::unique_ptr<jk_graph_s> g(new jk_graph_s());
+    g->device = h->device;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = jk_build(h, nd, D, J, K, &oc);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (rc == JK_OK && e2 != hipSuccess) rc = fail(JK_EDEVICE, "jk_graph_create: capture failed (%s)", hipGetErrorString(e2));
+        if (rc == JK_OK) {
+            e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = fail(JK_EDEVICE, "jk_graph_create: instantiate failed (%s)", hipGetErrorString(e));
+        }
+    } else {
+        rc = fail(JK_EDEVICE, "jk_graph_create: begin capture failed (%s)", hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != JK_OK) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        return rc;
+    }
+    *out = g.release();
+    return JK_OK;
+}
+
+int jk_graph_launch(jk_graph_t g, void* stream) {
+    if (!g) return fail(JK_EINVAL, "jk_graph_launch: NULL graph");
+    DeviceGuard dg;
+    int rc = dg.ok(g->device);
+    if (rc) return rc;
+    HIPC(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return JK_OK;
+}
+
+void jk_graph_destroy(jk_graph_t g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 int jk_profile_enable(jk_basis_t h, int32_t on) {
@@ -832,7 +1390,7 @@ int jk_profile_enable(jk_basis_t h, int32_t on) {
 }
 
 int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]) {
-    if (!h || !out || kind < 0 || kind > 1 || cls < 0 || cls >= kNumClass)
+    if (!h || !out || kind < 0 || kind > 3 || cls < 0 || cls >= kNumClass)
         return fail(JK_EINVAL, "jk_profile_read: bad arguments");
     std::lock_guard<std::mutex> g(h->mu);
     // fold every pending record into the accumulators; the start event of a

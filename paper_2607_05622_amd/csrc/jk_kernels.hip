@@ -92,22 +92,22 @@ __global__ void k_zero(double* __restrict__ p, long long n) {
 
 static inline unsigned blocks_for(long long n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
 
-hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s) {
-    if (a.nq <= 0) return hipSuccess;
+hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s, int fp32) {
+    if (a.nblocks <= 0) return hipSuccess;
     switch (cls) {
 #define JK_CASE(n) \
-    case n: return launch_eri_tile_c##n(a, s);
+    case n: return launch_eri_tile_c##n(a, s, fp32);
         JK_FOR_CLASS_INDEX(JK_CASE)
 #undef JK_CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s) {
-    if (a.nq <= 0) return hipSuccess;
+hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32) {
+    if (a.nblocks == 0) return hipSuccess;
     switch (cls) {
 #define JK_CASE(n) \
-    case n: return launch_digest_c##n(a, s);
+    case n: return launch_digest_c##n(a, s, fp32);
         JK_FOR_CLASS_INDEX(JK_CASE)
 #undef JK_CASE
         default: return hipErrorInvalidValue;

@@ -76,6 +76,28 @@ def load(path: str = LIB_PATH):
     lib.jk_eri_tiles.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     lib.jk_eri_tiles.restype = c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.jk_build_batch.argtypes = [ctypes.c_int32, pp, ctypes.POINTER(ctypes.c_int32), pp, pp, pp,
+                                   ctypes.POINTER(jk_build_opts)]
+    lib.jk_build_batch.restype = c_int
+    lib.jk_batch_workspace_bytes.argtypes = [ctypes.c_int32, pp, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(jk_build_opts)]
+    lib.jk_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.jk_autotune.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts), ctypes.c_char_p]
+    lib.jk_autotune.restype = c_int
+    lib.jk_tune_load.argtypes = [ctypes.c_char_p]
+    lib.jk_tune_load.restype = c_int
+    lib.jk_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.jk_tune_set.restype = c_int
+    lib.jk_tune_get.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.jk_tune_get.restype = c_int
+    lib.jk_graph_create.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.jk_graph_create.restype = c_int
+    lib.jk_graph_launch.argtypes = [vp, vp]
+    lib.jk_graph_launch.restype = c_int
+    lib.jk_graph_destroy.argtypes = [vp]
+    lib.jk_graph_destroy.restype = None
     lib.jk_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.jk_profile_enable.restype = c_int
     lib.jk_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
@@ -200,6 +222,84 @@ def jk_build(h, D, J=None, K=None, opts: jk_build_opts | None = None, stream=Non
     return J, K
 
 
+def _ptr_array(vals):
+    arr = (ctypes.c_void_p * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+def jk_batch_workspace_bytes(hs, nds, opts: jk_build_opts | None = None) -> int:
+    nd = (ctypes.c_int32 * len(nds))(*nds)
+    return int(load().jk_batch_workspace_bytes(len(hs), _ptr_array(hs), nd,
+                                               ctypes.byref(opts) if opts is not None else None))
+
+
+def jk_build_batch(hs, Ds, Js=None, Ks=None, opts: jk_build_opts | None = None, stream=None):
+    """One batched build over several molecules: hs handles, Ds list of
+    [nd_i, n_i, n_i] cuda float64 tensors.  Returns lists Js, Ks."""
+    import torch
+    o = opts if opts is not None else jk_default_opts()
+    nmol = len(hs)
+    if len(Ds) != nmol:
+        raise ValueError("one density tensor per handle")
+    ns = [jk_nbf(h) for h in hs]
+    Js = Js if Js is not None else ([torch.empty_like(D) for D in Ds] if o.want_j else [None] * nmol)
+    Ks = Ks if Ks is not None else ([torch.empty_like(D) for D in Ds] if o.want_k else [None] * nmol)
+    dps = [_dev_ptr(D, n, "D") for D, n in zip(Ds, ns)]
+    jps = [_dev_ptr(J, n, "J") if o.want_j else None for J, n in zip(Js, ns)]
+    kps = [_dev_ptr(K, n, "K") if o.want_k else None for K, n in zip(Ks, ns)]
+    s = stream if stream is not None else torch.cuda.current_stream(Ds[0].device)
+    o.stream = ctypes.c_void_p(s.cuda_stream)
+    nd = (ctypes.c_int32 * nmol)(*[int(D.shape[0]) for D in Ds])
+    _check(load().jk_build_batch(nmol, _ptr_array(hs), nd, _ptr_array(dps), _ptr_array(jps), _ptr_array(kps),
+                                 ctypes.byref(o)))
+    return Js, Ks
+
+
+def jk_autotune(h, D, J, K, opts: jk_build_opts | None = None, cache_path: str | None = None, stream=None):
+    import torch
+    n = jk_nbf(h)
+    o = opts if opts is not None else jk_default_opts()
+    s = stream if stream is not None else torch.cuda.current_stream(D.device)
+    o.stream = ctypes.c_void_p(s.cuda_stream)
+    _check(load().jk_autotune(h, int(D.shape[0]), _dev_ptr(D, n, "D"), _dev_ptr(J, n, "J"), _dev_ptr(K, n, "K"),
+                              ctypes.byref(o), cache_path.encode() if cache_path else None))
+
+
+def jk_tune_load(path: str) -> None:
+    _check(load().jk_tune_load(path.encode()))
+
+
+def jk_tune_set(cls: int, seg_max: int, g_max: int) -> None:
+    _check(load().jk_tune_set(cls, seg_max, g_max))
+
+
+def jk_tune_get(cls: int) -> tuple:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().jk_tune_get(cls, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def jk_graph_create(h, D, J, K, opts: jk_build_opts) -> int:
+    """Capture one build into a HIP graph (opts.workspace required)."""
+    n = jk_nbf(h)
+    g = ctypes.c_void_p()
+    _check(load().jk_graph_create(h, int(D.shape[0]), _dev_ptr(D, n, "D"), _dev_ptr(J, n, "J") if opts.want_j else None,
+                                  _dev_ptr(K, n, "K") if opts.want_k else None, ctypes.byref(opts), ctypes.byref(g)))
+    return g.value
+
+
+def jk_graph_launch(g, stream=None) -> None:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().jk_graph_launch(g, ctypes.c_void_p(s.cuda_stream)))
+
+
+def jk_graph_destroy(g) -> None:
+    load().jk_graph_destroy(g)
+
+
 def jk_profile_enable(h, on: bool) -> None:
     _check(load().jk_profile_enable(h, 1 if on else 0))
 
@@ -235,9 +335,9 @@ class JKBasis:
         self.h = jk_create_basis(basis)
         self.nbf = jk_nbf(self.h)
 
-    def build(self, D, J=None, K=None, **opts):
+    def build(self, D, J=None, K=None, stream=None, **opts):
         o = jk_default_opts(**opts) if opts else None
-        return jk_build(self.h, D, J, K, o)
+        return jk_build(self.h, D, J, K, o, stream)
 
     def eri_tiles(self, shells):
         arrays = self.basis.as_arrays() if hasattr(self.basis, "as_arrays") else self.basis

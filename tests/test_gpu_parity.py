@@ -196,3 +196,217 @@ def test_medium_workload_sampled_blocks(dev):
         assert maxabs(K[:, fo[a]:fo[a + 1], fo[c]:fo[c + 1]], Kb) <= TOL, (a, c)
     # properties that hold at any size
     assert maxabs(J, J.transpose(0, 2, 1)) <= 1e-12 * np.max(np.abs(J))
+
+
+# ------------------------------------------------------------ mixed tier ----
+
+def rel_frob(a, b):
+    """Per-density ||a - b||_F / ||b||_F."""
+    return np.sqrt(np.sum((a - b) ** 2, axis=(1, 2)) / np.maximum(np.sum(b ** 2, axis=(1, 2)), 1e-300))
+
+
+def test_mixed_precision_against_oracle(dev):
+    b = synth.random_basis(808, 8, 5)
+    D = synth.random_densities(8, 6, b.nbf())
+    Jr, Kr = oracle.jk(b, D, 1e-12)
+    h = jk.JKBasis(b)
+    import torch
+    Dt = torch.tensor(D, device=dev)
+    J, K = h.build(Dt, precision=jk.JK_MIXED)
+    torch.cuda.synchronize()
+    st = h.stats()
+    h.close()
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    assert st["quartets_fp32"] > 0.3 * st["quartets"]        # the FP32 tier is exercised
+    assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8)
+    print("mixed: max rel-Frobenius J %.2e K %.2e, max-abs J %.2e K %.2e" % (
+        rel_frob(J, Jr).max(), rel_frob(K, Kr).max(), maxabs(J, Jr), maxabs(K, Kr)))
+
+
+def test_mixed_bound_zero_is_fp64(dev):
+    b = synth.random_basis(809, 5, 3)
+    D = synth.random_densities(9, 3, b.nbf())
+    J1, K1 = gpu_jk(b, D, dev)
+    J2, K2 = gpu_jk(b, D, dev, precision=jk.JK_MIXED, fp32_bound=0.0)
+    assert maxabs(J1, J2) <= 1e-13 and maxabs(K1, K2) <= 1e-13
+
+
+def test_mixed_medium_workload(dev):
+    """312 AO, 16 densities: mixed against the GPU's own FP64 build (whole
+    matrices) and against the oracle on sampled blocks."""
+    w = synth.config1()
+    J64, K64 = gpu_jk(w.basis, w.D, dev)
+    Jm, Km = gpu_jk(w.basis, w.D, dev, precision=jk.JK_MIXED)
+    assert np.all(rel_frob(Jm, J64) <= 1e-8) and np.all(rel_frob(Km, K64) <= 1e-8)
+    fo = w.basis.func_offsets()
+    pairs = [(0, 0), (40, 7), (143, 60), (100, 130)]
+    for (a, c), (Jb, Kb) in zip(pairs, oracle.jk_blocks(w.basis, w.D, pairs, 1e-12)):
+        sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
+        scale_j = np.max(np.abs(J64), axis=(1, 2))[:, None, None]
+        scale_k = np.max(np.abs(K64), axis=(1, 2))[:, None, None]
+        assert np.all(np.abs(Jm[sl] - Jb) <= 1e-8 * scale_j)
+        assert np.all(np.abs(Km[sl] - Kb) <= 1e-8 * scale_k)
+
+
+# ------------------------------------------------------- batched launch ----
+
+def _batch(bases, Ds, dev, **opts):
+    import torch
+    hs = [jk.JKBasis(b) for b in bases]
+    try:
+        Dt = [torch.tensor(D, device=dev) for D in Ds]
+        o = jk.jk_default_opts(**opts)
+        Js, Ks = jk.jk_build_batch([h.h for h in hs], Dt, opts=o)
+        torch.cuda.synchronize()
+        return [J.cpu().numpy() for J in Js], [K.cpu().numpy() for K in Ks]
+    finally:
+        for h in hs:
+            h.close()
+
+
+def test_batch_uneven_molecules(dev):
+    specs = [(1, 1, 3), (3, 2, 1), (5, 3, 8), (2, 2, 17), (4, 1, 5), (6, 4, 2)]
+    bases = [synth.random_basis(900 + i, na, nh) for i, (na, nh, _) in enumerate(specs)]
+    Ds = [synth.random_densities(950 + i, nd, b.nbf()) for i, (b, (_, _, nd)) in enumerate(zip(bases, specs))]
+    Jb, Kb = _batch(bases, Ds, dev)
+    for b, D, J, K in zip(bases, Ds, Jb, Kb):
+        Jr, Kr = oracle.jk(b, D, 1e-12)
+        assert maxabs(J, Jr) <= TOL and maxabs(K, Kr) <= TOL
+        Js, Ks = gpu_jk(b, D, dev)
+        assert maxabs(J, Js) <= 1e-13 and maxabs(K, Ks) <= 1e-13
+
+
+def test_batch_mixed_precision(dev):
+    bases = [synth.random_basis(970 + i, 4 + 2 * i, 3 + i) for i in range(3)]
+    Ds = [synth.random_densities(980 + i, 4 + 3 * i, b.nbf()) for i, b in enumerate(bases)]
+    Jb, Kb = _batch(bases, Ds, dev, precision=jk.JK_MIXED)
+    for b, D, J, K in zip(bases, Ds, Jb, Kb):
+        Jr, Kr = oracle.jk(b, D, 1e-12)
+        assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8)
+
+
+def test_batch_workload_64_molecules(dev):
+    """The 64-molecule uneven workload in one batched build: every molecule
+    equals its own build; the eight smallest against the oracle."""
+    ws = synth.config3()
+    bases = [w.basis for w in ws]
+    Ds = [w.D for w in ws]
+    Jb, Kb = _batch(bases, Ds, dev)
+    order = np.argsort([b.nbf() for b in bases])
+    for i in range(len(ws)):
+        Js, Ks = gpu_jk(bases[i], Ds[i], dev)
+        assert maxabs(Jb[i], Js) <= 1e-12 and maxabs(Kb[i], Ks) <= 1e-12, i
+    for i in order[:8]:
+        Jr, Kr = oracle.jk(bases[i], Ds[i], 1e-12)
+        assert maxabs(Jb[i], Jr) <= TOL and maxabs(Kb[i], Kr) <= TOL, i
+
+
+# ------------------------------------------------------------ HIP graphs ----
+
+def test_graph_replays_match_eager_builds(dev):
+    import torch
+    b = synth.random_basis(1111, 5, 3)
+    h = jk.JKBasis(b)
+    nd = 6
+    n = b.nbf
+    o = jk.jk_default_opts()
+    nbytes = jk.jk_workspace_bytes(h.h, nd, o)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = nbytes
+    D = torch.zeros(nd, n, n, dtype=torch.float64, device=dev)
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    g = jk.jk_graph_create(h.h, D, J, K, o)
+    s = torch.cuda.Stream(device=dev)
+    for rep in range(4):
+        Dn = torch.tensor(synth.random_densities(1200 + rep, nd, n), device=dev)
+        D.copy_(Dn)
+        torch.cuda.synchronize()
+        jk.jk_graph_launch(g, s)
+        s.synchronize()
+        Jg, Kg = J.clone(), K.clone()
+        Je, Ke = h.build(Dn.clone())          # eager build between replays
+        torch.cuda.synchronize()
+        assert float((Jg - Je).abs().max()) <= 1e-13 and float((Kg - Ke).abs().max()) <= 1e-13, rep
+    jk.jk_graph_destroy(g)
+    h.close()
+
+
+# --------------------------------------------------------------- serving ----
+
+def _requests(bases, dev, n, rate, seed):
+    import torch
+    from paper_2607_05622_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for i in range(n):
+        m = int(rng.integers(len(bases)))
+        nd = int(np.floor(np.exp(rng.uniform(0, np.log(17)))))
+        D = torch.tensor(synth.random_densities(seed * 1000 + i, nd, bases[m].nbf()), device=dev)
+        out.append(Request(i, float(t[i]), m, D))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_results_equal_alone(dev, precision):
+    """Requests served in the mix (batched launches, graphs, overlapping
+    slots) equal the same requests built alone."""
+    from paper_2607_05622_amd.serve import JKServer
+    bases = [synth.random_basis(1300 + i, 2 + 2 * i, 1 + i) for i in range(4)]
+    srv = JKServer(bases, n_slots=3, mem_budget=3 * (256 << 20), precision=precision, max_batch=6)
+    srv.warm_graphs(max_nd=16)
+    reqs = _requests(bases, dev, 40, rate=400.0, seed=7)
+    stats = srv.run(reqs)
+    assert stats["requests"] == 40 and stats["mean_batch"] > 1.0
+    assert srv.peak_admitted <= srv.slot_bytes
+    for r in reqs:
+        Ja, Ka = gpu_jk(bases[r.mol], r.D.cpu().numpy(), dev, precision=precision)
+        J, K = r.J.cpu().numpy(), r.K.cpu().numpy()
+        if precision == 0:
+            assert maxabs(J, Ja) <= 1e-12 and maxabs(K, Ka) <= 1e-12, r.index
+        else:
+            assert np.all(rel_frob(J, Ja) <= 1e-8) and np.all(rel_frob(K, Ka) <= 1e-8), r.index
+    srv.close()
+
+
+def test_served_low_budget_waits_but_completes(dev):
+    from paper_2607_05622_amd.serve import JKServer
+    bases = [synth.random_basis(1400 + i, 3 + i, 2) for i in range(2)]
+    reqs = _requests(bases, dev, 12, rate=1000.0, seed=9)
+    srv = JKServer(bases, n_slots=1, mem_budget=64 << 20, precision=0, max_batch=8, use_graphs=False)
+    alone = max(srv.workspace_bytes([r]) for r in reqs)
+    srv.close()
+    # a budget that holds one request at a time
+    srv = JKServer(bases, n_slots=1, mem_budget=alone + 4096, precision=0, max_batch=8, use_graphs=False)
+    stats = srv.run(reqs)
+    assert stats["requests"] == 12 and srv.peak_admitted <= srv.slot_bytes
+    for r in reqs:
+        Jr, Kr = oracle.jk(bases[r.mol], r.D.cpu().numpy(), 1e-12)
+        assert maxabs(r.J.cpu().numpy(), Jr) <= TOL and maxabs(r.K.cpu().numpy(), Kr) <= TOL
+    srv.close()
+
+
+def test_autotune_keeps_results(dev, tmp_path):
+    import torch
+    b = synth.random_basis(1500, 6, 4)
+    D = synth.random_densities(1501, 9, b.nbf())
+    Jr, Kr = oracle.jk(b, D, 1e-12)
+    old = [jk.jk_tune_get(c) for c in range(21)]
+    h = jk.JKBasis(b)
+    try:
+        Dt = torch.tensor(D, device=dev)
+        J = torch.empty_like(Dt)
+        K = torch.empty_like(Dt)
+        path = str(tmp_path / "tune.json")
+        jk.jk_autotune(h.h, Dt, J, K, cache_path=path)
+        assert '"arch": "gfx950"' in open(path).read()
+        J, K = h.build(Dt)
+        torch.cuda.synchronize()
+        assert maxabs(J.cpu().numpy(), Jr) <= TOL and maxabs(K.cpu().numpy(), Kr) <= TOL
+        jk.jk_tune_load(path)
+    finally:
+        h.close()
+        for c, (sm, gm) in enumerate(old):
+            jk.jk_tune_set(c, sm, gm)
