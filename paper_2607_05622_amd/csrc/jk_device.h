@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
 // Digestion of one quartet for one density; OUTER is the unroll pragma of
 // the loops over output elements (full unroll keeps a register tile in
 // registers, no unroll keeps large tiles streaming from memory).
-#define JK_DIGEST_QUARTET(OUTER) \
+#define JK_DIGEST_QUARTET(OUTER, DK) \
             if (a.want_j) { \
                 /* J_ab += w sum_kl I (D_kl + D_lk); J_cd += w sum_ij I (D_ij + D_ji) */ \
 OUTER \
@@ -339,7 +339,7 @@ _Pragma("unroll") \
                             for (int j = 0; j < NB; ++j) { \
                                 const double v = I(i, j, k, l); \
                                 jacc[i * NB + j] = fma(v, s2, jacc[i * NB + j]); \
-                                t = fma(v, Dv(fa + i, fb + j) + Dv(fb + j, fa + i), t); \
+                                t = fma(v, s2ab[i * NB + j], t); \
                             } \
                         unsafeAtomicAdd(Jm + ((fc + k) * nc + fd + l) * ndp, w * t); \
                     } \
@@ -357,8 +357,8 @@ _Pragma("unroll") \
 _Pragma("unroll") \
                             for (int l = 0; l < ND; ++l) { \
                                 const double v = I(i, j, k, l); \
-                                s1 = fma(v, Dv(fb + j, fd + l), s1); \
-                                s2 = fma(v, Dv(fd + l, fb + j), s2); \
+                                s1 = fma(v, DK(NA + j, cd + l, fb + j, fd + l), s1); \
+                                s2 = fma(v, DK(2 * NA + NB + j, cd + l, fd + l, fb + j), s2); \
                             } \
                         atomicAdd(S(i, cc + k), w * s1); \
                         atomicAdd(S(NA + NB + i, cc + k), w * s2); \
@@ -371,8 +371,8 @@ _Pragma("unroll") \
 _Pragma("unroll") \
                             for (int k = 0; k < NC; ++k) { \
                                 const double v = I(i, j, k, l); \
-                                s1 = fma(v, Dv(fb + j, fc + k), s1); \
-                                s2 = fma(v, Dv(fc + k, fb + j), s2); \
+                                s1 = fma(v, DK(NA + j, cc + k, fb + j, fc + k), s1); \
+                                s2 = fma(v, DK(2 * NA + NB + j, cc + k, fc + k, fb + j), s2); \
                             } \
                         atomicAdd(S(i, cd + l), w * s1); \
                         atomicAdd(S(NA + NB + i, cd + l), w * s2); \
@@ -390,8 +390,8 @@ _Pragma("unroll") \
 _Pragma("unroll") \
                             for (int l = 0; l < ND; ++l) { \
                                 const double v = I(i, j, k, l); \
-                                s1 = fma(v, Dv(fa + i, fd + l), s1); \
-                                s2 = fma(v, Dv(fd + l, fa + i), s2); \
+                                s1 = fma(v, DK(i, cd + l, fa + i, fd + l), s1); \
+                                s2 = fma(v, DK(NA + NB + i, cd + l, fd + l, fa + i), s2); \
                             } \
                         atomicAdd(S(NA + j, cc + k), w * s1); \
                         atomicAdd(S(2 * NA + NB + j, cc + k), w * s2); \
@@ -404,8 +404,8 @@ _Pragma("unroll") \
 _Pragma("unroll") \
                             for (int k = 0; k < NC; ++k) { \
                                 const double v = I(i, j, k, l); \
-                                s1 = fma(v, Dv(fa + i, fc + k), s1); \
-                                s2 = fma(v, Dv(fc + k, fa + i), s2); \
+                                s1 = fma(v, DK(i, cc + k, fa + i, fc + k), s1); \
+                                s2 = fma(v, DK(NA + NB + i, cc + k, fc + k, fa + i), s2); \
                             } \
                         atomicAdd(S(NA + j, cd + l), w * s1); \
                         atomicAdd(S(2 * NA + NB + j, cd + l), w * s2); \
@@ -442,11 +442,14 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
     const int gn = min(G, m.nd - x0);
     const int W = it.colAw + it.colBw;
     const int nstrip = a.want_k ? R * G * W : 0;
-    double* __restrict__ strips = lds;            // [R][G][W]
-    double* __restrict__ jab = lds + nstrip;      // [NA*NB][G]
-    const int nlds = nstrip + (a.want_j ? NA * NB * G : 0);
-    for (int i = threadIdx.x; i < nlds; i += blockDim.x) lds[i] = 0.0;
-    __syncthreads();
+    const bool dstrip = a.want_k && it.dstrip;
+    double* __restrict__ strips = lds;                          // K strips [R][G][W]
+    double* __restrict__ dstr = lds + nstrip;                   // D strips [R][G][W] (dstrip)
+    double* __restrict__ jab = dstr + (dstrip ? nstrip : 0);    // [NA*NB][G]
+    const int nzero = nstrip;
+    for (int i = threadIdx.x; i < nzero; i += blockDim.x) lds[i] = 0.0;
+    if (a.want_j)
+        for (int i = threadIdx.x; i < NA * NB * G; i += blockDim.x) jab[i] = 0.0;
 
     const int2 sg = it.seg;
     const long long q0 = sg.x - it.chunk_q0;     // tile index of the segment's first quartet
@@ -459,6 +462,27 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
     const long long nc = m.nc, ndp = m.nd, nq = it.chunk_n;
     const int colA0 = it.colA0, colAw = it.colAw, colB0 = it.colB0;
     auto lcol = [&](int col) { return (col >= colA0 && col < colA0 + colAw) ? col - colA0 : colAw + (col - colB0); };
+    if (dstrip) {
+        // D strips: rows of a and b, then columns of a and b, over the windows
+        for (int idx = threadIdx.x; idx < R * G * W; idx += blockDim.x) {
+            const int c = idx % W;
+            const int rg = idx / W;
+            const int gg = rg % G, r = rg / G;
+            const int col = c < colAw ? colA0 + c : colB0 + (c - colAw);
+            double v = 0.0;
+            if (gg < gn) {
+                const long long x = x0 + gg;
+                long long row, cl;
+                if (r < NA) { row = fa + r; cl = col; }
+                else if (r < NA + NB) { row = fb + r - NA; cl = col; }
+                else if (r < 2 * NA + NB) { row = col; cl = fa + r - NA - NB; }
+                else { row = col; cl = fb + r - 2 * NA - NB; }
+                v = m.D[(row * nc + cl) * ndp + x];
+            }
+            dstr[idx] = v;
+        }
+    }
+    __syncthreads();
     double jacc[NA * NB];
 #pragma unroll
     for (int e = 0; e < NA * NB; ++e) jacc[e] = 0.0;
@@ -469,6 +493,14 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
         double* __restrict__ Jm = m.J + x;
         double* __restrict__ sA = strips + static_cast<long long>(g) * W;   // row block 0, density g
         auto S = [&](int row, int col) -> double* { return sA + static_cast<long long>(row) * G * W + col; };
+        const double* __restrict__ dA = dstr + static_cast<long long>(g) * W;
+        auto DKL = [&](int r, int lc, int, int) -> double { return dA[static_cast<long long>(r) * G * W + lc]; };
+        auto DKG = [&](int, int, int row, int col) -> double { return Dv(row, col); };
+        double s2ab[NA * NB];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) s2ab[i * NB + j] = Dv(fa + i, fb + j) + Dv(fb + j, fa + i);
 #pragma unroll 1
         for (int qi = slot; qi < sg.y; qi += slots) {
             const long long q = q0 + qi;
@@ -492,10 +524,18 @@ __global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
             };
             const int fc = Q.fa, fd = Q.fb;
             const int cc = lcol(fc), cd = lcol(fd);
-            if constexpr (kRegTile) {
-                JK_DIGEST_QUARTET(_Pragma("unroll"))
+            if (dstrip) {
+                if constexpr (kRegTile) {
+                    JK_DIGEST_QUARTET(_Pragma("unroll"), DKL)
+                } else {
+                    JK_DIGEST_QUARTET(_Pragma("unroll 1"), DKL)
+                }
             } else {
-                JK_DIGEST_QUARTET(_Pragma("unroll 1"))
+                if constexpr (kRegTile) {
+                    JK_DIGEST_QUARTET(_Pragma("unroll"), DKG)
+                } else {
+                    JK_DIGEST_QUARTET(_Pragma("unroll 1"), DKG)
+                }
             }
 }
         if (a.want_j) {

@@ -470,11 +470,14 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_c
                 const double prim_avg = prim_tier / static_cast<double>(std::max<long long>(nq_tier, 1));
                 const int colA0 = h->lw_off[lc], colAw = h->lw_len[lc];
                 const int colB0 = ld != lc ? h->lw_off[ld] : 0, colBw = ld != lc ? h->lw_len[ld] : 0;
-                const size_t per_density = sizeof(double) * ((o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0) +
-                                                             (o->want_j ? NA * NB : 0));
-                if (per_density > static_cast<size_t>(lds_cap))
+                const size_t strip = sizeof(double) * (o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0);
+                const size_t jpart = sizeof(double) * (o->want_j ? NA * NB : 0);
+                if (strip + jpart > static_cast<size_t>(lds_cap))
                     return fail(JK_EUNSUPPORTED, "class %d of a %d-function basis needs %zu bytes of LDS per density "
-                                "(limit %d)", c, h->nc, per_density, lds_cap);
+                                "(limit %d)", c, h->nc, strip + jpart, lds_cap);
+                // stage the density strips in LDS as well when they fit
+                const int dstrip = o->want_k && 2 * strip + jpart <= static_cast<size_t>(lds_cap);
+                const size_t per_density = (dstrip ? 2 * strip : strip) + jpart;
                 int G = 16;
                 const int gmax = tune_of(c).g_max;
                 while (G > 1 && (G > gmax || G / 2 >= nd || G * per_density > static_cast<size_t>(lds_cap))) G /= 2;
@@ -517,6 +520,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_c
                         d.colAw = colAw;
                         d.colB0 = colB0;
                         d.colBw = colBw;
+                        d.dstrip = dstrip;
                         wp.dig.push_back(d);
                         L.ndig++;
                     }

@@ -69,6 +69,7 @@ struct DigItem {
     long long tile_off;     // element offset of that item's tiles
     int mol, G, ngroups, kstart;   // kstart: first block index within this item's XCD
     int colA0, colAw, colB0, colBw;   // LDS column windows (ket shells' functions)
+    int dstrip, pad;                  // 1: density strips staged in LDS too
 };
 
 struct DigestArgs {

@@ -254,39 +254,58 @@ def _prim_norm(a, l):
 
 
 def overlap_matrix(basis: Basis) -> np.ndarray:
-    """Overlap matrix in the basis' own functions (pure d if spherical)."""
+    """Overlap matrix in the basis' own functions (pure d if spherical).
+
+    Vectorized over all shell pairs of one (l_a, l_b) combination and their
+    primitive pairs."""
     po = basis.prim_offsets()
     ns = basis.nshells
-    cart_blocks = []
+    npmax = int(basis.shell_nprim.max())
+    ls = np.asarray(basis.shell_l)
+    # padded primitive tables: exponents (1.0 where absent) and weights (0)
+    ex = np.ones((ns, npmax))
+    wt = np.zeros((ns, npmax))
     for s in range(ns):
-        l = int(basis.shell_l[s])
-        ex = basis.exps[po[s]:po[s + 1]]
+        l = int(ls[s])
+        e = basis.exps[po[s]:po[s + 1]]
         c = basis.coefs[po[s]:po[s + 1]]
-        cart_blocks.append((l, basis.xyz[basis.shell_atom[s]], ex,
-                            c * _prim_norm(ex, l) * _contraction_scale(ex, c, l)))
-    ncart = [len(CART[b[0]]) for b in cart_blocks]
+        ex[s, :len(e)] = e
+        wt[s, :len(e)] = c * _prim_norm(e, l) * _contraction_scale(e, c, l)
+    cen = basis.xyz[basis.shell_atom]
+    ncart = np.array([len(CART[int(l)]) for l in ls])
     co = np.concatenate([[0], np.cumsum(ncart)])
     S = np.zeros((co[-1], co[-1]))
-    for i in range(ns):
-        li, A, ea, ca = cart_blocks[i]
-        for j in range(i + 1):
-            lj, B, eb, cb = cart_blocks[j]
-            a = ea[:, None]
-            b = eb[None, :]
+    for li in range(int(ls.max()) + 1):
+        for lj in range(li + 1):
+            I = np.nonzero(ls == li)[0]
+            Jn = np.nonzero(ls == lj)[0]
+            ii, jj = np.meshgrid(I, Jn, indexing="ij")
+            ii, jj = ii.ravel(), jj.ravel()
+            if li == lj:
+                keep = ii >= jj
+                ii, jj = ii[keep], jj[keep]
+            if len(ii) == 0:
+                continue
+            a = ex[ii][:, :, None]          # [npair, npa, 1]
+            b = ex[jj][:, None, :]          # [npair, 1, npb]
             p = a + b
-            mu = a * b / p
-            blk = np.zeros((len(CART[li]), len(CART[lj])))
+            A = cen[ii]
+            B = cen[jj]
+            ab2 = np.sum((A - B) ** 2, axis=1)[:, None, None]
+            pref = (np.pi / p) ** 1.5 * np.exp(-a * b / p * ab2)
+            w = wt[ii][:, :, None] * wt[jj][:, None, :] * pref
             tabs = []
             for k in range(3):
-                P = (a * A[k] + b * B[k]) / p
-                tabs.append(_os_overlap_1d(li, lj, P - A[k], P - B[k], p))
-            pref = (np.pi / p) ** 1.5 * np.exp(-mu * float(np.sum((A - B) ** 2)))
-            w = ca[:, None] * cb[None, :] * pref
+                P = (a * A[:, k, None, None] + b * B[:, k, None, None]) / p
+                tabs.append(_os_overlap_1d(li, lj, P - A[:, k, None, None], P - B[:, k, None, None], p))
+            blk = np.zeros((len(ii), len(CART[li]), len(CART[lj])))
             for u, (ax, ay, az) in enumerate(CART[li]):
                 for v, (bx, by, bz) in enumerate(CART[lj]):
-                    blk[u, v] = float(np.sum(w * tabs[0][ax, bx] * tabs[1][ay, by] * tabs[2][az, bz]))
-            S[co[i]:co[i + 1], co[j]:co[j + 1]] = blk
-            S[co[j]:co[j + 1], co[i]:co[i + 1]] = blk.T
+                    blk[:, u, v] = np.sum(w * tabs[0][ax, bx] * tabs[1][ay, by] * tabs[2][az, bz], axis=(1, 2))
+            for t in range(len(ii)):
+                i, j = ii[t], jj[t]
+                S[co[i]:co[i + 1], co[j]:co[j + 1]] = blk[t]
+                S[co[j]:co[j + 1], co[i]:co[i + 1]] = blk[t].T
     T = cart_to_basis_matrix(basis)
     return T.T @ S @ T
 
