@@ -49,8 +49,10 @@ def workload(name):
 
 def cpu_baseline(w, stride):
     import oracle
-    n_cores = os.cpu_count() or 1
-    oracle.set_threads(n_cores)
+    n_cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        n_cores = min(n_cores, int(os.environ["OMP_NUM_THREADS"]))
+    oracle.set_threads(max(1, n_cores))
     t0 = time.perf_counter()
     _, _, done, total = oracle.jk_sample(w.basis, w.D, stride, 0, 1e-12)
     dt = time.perf_counter() - t0
@@ -126,7 +128,7 @@ def main():
                     help="serve a Poisson request stream over 16 resident molecules instead")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--rate", type=float, default=1.0, help="arrival rate / FP64 one-at-a-time capacity")
-    ap.add_argument("--cpu-stride", type=int, default=64)
+    ap.add_argument("--cpu-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

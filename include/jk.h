@@ -125,9 +125,10 @@ size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t
                                 const jk_build_opts* o);
 
 /* Schedule autotuning.  Per canonical class the library keeps two launch
- * parameters: the length cap of a digestion segment (a run of quartets with
- * one bra pair handled by one workgroup) and the cap on the densities a
- * digestion workgroup takes at once (1, 2, 4, 8 or 16).  jk_autotune times
+ * parameters: seg_max, the length cap of a digestion piece (quartets of one
+ * bra pair digested by one wave), and g_max, the densities a digestion wave
+ * takes at once (16; any of 1, 2, 4, 8 selects 8, which is also used when
+ * a build has at most 8 densities).  jk_autotune times
  * every candidate pair on the given build with the event profiler, keeps
  * the fastest per class, applies it process-wide and, if cache_path is not
  * NULL, writes it as JSON keyed by GPU architecture and class;

@@ -1,7 +1,7 @@
 // One canonical shell-quartet class per translation unit: compiled once per
 // class index with -DJK_CLASS_INDEX=n so the generated recurrences build in
 // parallel.  Defines launch_eri_tile_c<n> and launch_digest_c<n>.
-#include "jk_device.h"
+#include "jk_digest.h"
 
 #ifndef JK_CLASS_INDEX
 #error "compile with -DJK_CLASS_INDEX=<0..20>"
@@ -24,8 +24,16 @@ hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
 }
 
 template <int la, int lb, int lc, int ld, typename TT>
-hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_digest<la, lb, lc, ld, TT>), dim3(a.nblocks), dim3(256), a.lds_bytes, s, a);
+hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16) {
+    constexpr int wpb = DigShape<la, lb, lc, ld>::WPB;
+    const dim3 grid(a.nblocks), block(64 * wpb);
+    if (pass == 0) {
+        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+    } else {
+        if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -34,18 +42,9 @@ hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s) {
         return fp32 ? launch_eri_tpl<Eri##tag<float>, float>(a, s)                                 \
                     : launch_eri_tpl<Eri##tag<double>, double>(a, s);                              \
     }                                                                                              \
-    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s, int fp32) {      \
-        return fp32 ? launch_digest_tpl<la, lb, lc, ld, float>(a, s)                               \
-                    : launch_digest_tpl<la, lb, lc, ld, double>(a, s);                             \
-    }                                                                                              \
-    hipError_t JK_PASTE(digest_prepare_c, idx)(size_t lds_bytes) {                                 \
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld, double>), \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,             \
-                                           static_cast<int>(lds_bytes));                           \
-        if (e != hipSuccess) return e;                                                             \
-        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_digest<la, lb, lc, ld, float>), \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,                     \
-                                   static_cast<int>(lds_bytes));                                   \
+    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16) { \
+        return fp32 ? launch_digest_tpl<la, lb, lc, ld, float>(a, s, pass, g16)                    \
+                    : launch_digest_tpl<la, lb, lc, ld, double>(a, s, pass, g16);                  \
     }
 
 #define JK_SELECT(idx, tag, la, lb, lc, ld) JK_SELECT_##idx(idx, tag, la, lb, lc, ld)

@@ -1,6 +1,7 @@
 // Device-side building blocks of the J/K build: FP64 Boys function,
 // primitive-quartet set-up, the screening decision, and the per-class ERI tile
-// and digestion kernels (instantiated once per class in jk_class.hip).
+// kernel (instantiated once per class in jk_class.hip; digestion is in
+// jk_digest.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -316,259 +317,6 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
         const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
         if constexpr (C::kSplit) eri_one_split<C, R>(a, m, it, q);
         else eri_one<C, R>(a, m, it, q);
-    }
-}
-
-// -------------------------------------------------------------- digest ---
-
-// Digestion of one quartet for one density; OUTER is the unroll pragma of
-// the loops over output elements (full unroll keeps a register tile in
-// registers, no unroll keeps large tiles streaming from memory).
-#define JK_DIGEST_QUARTET(OUTER, DK) \
-            if (a.want_j) { \
-                /* J_ab += w sum_kl I (D_kl + D_lk); J_cd += w sum_ij I (D_ij + D_ji) */ \
-OUTER \
-                for (int k = 0; k < NC; ++k) \
-OUTER \
-                    for (int l = 0; l < ND; ++l) { \
-                        const double s2 = w * (Dv(fc + k, fd + l) + Dv(fd + l, fc + k)); \
-                        double t = 0.0; \
-_Pragma("unroll") \
-                        for (int i = 0; i < NA; ++i) \
-_Pragma("unroll") \
-                            for (int j = 0; j < NB; ++j) { \
-                                const double v = I(i, j, k, l); \
-                                jacc[i * NB + j] = fma(v, s2, jacc[i * NB + j]); \
-                                t = fma(v, s2ab[i * NB + j], t); \
-                            } \
-                        unsafeAtomicAdd(Jm + ((fc + k) * nc + fd + l) * ndp, w * t); \
-                    } \
-            } \
-            if (a.want_k) { \
-                /* rows of a: K_ac[i][k] += sum_jl I D_bd[j][l]; K_ad[i][l] += sum_jk I D_bc[j][k] */ \
-                /* cols of a: K_ca[k][i] += sum_jl I D_db[l][j]; K_da[l][i] += sum_jk I D_cb[k][j] */ \
-OUTER \
-                for (int i = 0; i < NA; ++i) { \
-OUTER \
-                    for (int k = 0; k < NC; ++k) { \
-                        double s1 = 0.0, s2 = 0.0; \
-_Pragma("unroll") \
-                        for (int j = 0; j < NB; ++j) \
-_Pragma("unroll") \
-                            for (int l = 0; l < ND; ++l) { \
-                                const double v = I(i, j, k, l); \
-                                s1 = fma(v, DK(NA + j, cd + l, fb + j, fd + l), s1); \
-                                s2 = fma(v, DK(2 * NA + NB + j, cd + l, fd + l, fb + j), s2); \
-                            } \
-                        atomicAdd(S(i, cc + k), w * s1); \
-                        atomicAdd(S(NA + NB + i, cc + k), w * s2); \
-                    } \
-OUTER \
-                    for (int l = 0; l < ND; ++l) { \
-                        double s1 = 0.0, s2 = 0.0; \
-_Pragma("unroll") \
-                        for (int j = 0; j < NB; ++j) \
-_Pragma("unroll") \
-                            for (int k = 0; k < NC; ++k) { \
-                                const double v = I(i, j, k, l); \
-                                s1 = fma(v, DK(NA + j, cc + k, fb + j, fc + k), s1); \
-                                s2 = fma(v, DK(2 * NA + NB + j, cc + k, fc + k, fb + j), s2); \
-                            } \
-                        atomicAdd(S(i, cd + l), w * s1); \
-                        atomicAdd(S(NA + NB + i, cd + l), w * s2); \
-                    } \
-                } \
-                /* rows of b: K_bc[j][k] += sum_il I D_ad[i][l]; K_bd[j][l] += sum_ik I D_ac[i][k] */ \
-                /* cols of b: K_cb[k][j] += sum_il I D_da[l][i]; K_db[l][j] += sum_ik I D_ca[k][i] */ \
-OUTER \
-                for (int j = 0; j < NB; ++j) { \
-OUTER \
-                    for (int k = 0; k < NC; ++k) { \
-                        double s1 = 0.0, s2 = 0.0; \
-_Pragma("unroll") \
-                        for (int i = 0; i < NA; ++i) \
-_Pragma("unroll") \
-                            for (int l = 0; l < ND; ++l) { \
-                                const double v = I(i, j, k, l); \
-                                s1 = fma(v, DK(i, cd + l, fa + i, fd + l), s1); \
-                                s2 = fma(v, DK(NA + NB + i, cd + l, fd + l, fa + i), s2); \
-                            } \
-                        atomicAdd(S(NA + j, cc + k), w * s1); \
-                        atomicAdd(S(2 * NA + NB + j, cc + k), w * s2); \
-                    } \
-OUTER \
-                    for (int l = 0; l < ND; ++l) { \
-                        double s1 = 0.0, s2 = 0.0; \
-_Pragma("unroll") \
-                        for (int i = 0; i < NA; ++i) \
-_Pragma("unroll") \
-                            for (int k = 0; k < NC; ++k) { \
-                                const double v = I(i, j, k, l); \
-                                s1 = fma(v, DK(i, cc + k, fa + i, fc + k), s1); \
-                                s2 = fma(v, DK(NA + NB + i, cc + k, fc + k, fa + i), s2); \
-                            } \
-                        atomicAdd(S(NA + j, cd + l), w * s1); \
-                        atomicAdd(S(2 * NA + NB + j, cd + l), w * s2); \
-                    } \
-                } \
-            } \
-        
-
-template <int LA, int LB, int LC, int LD, typename TT>
-__global__ __launch_bounds__(256) void k_digest(DigestArgs a) {
-    extern __shared__ double lds[];
-    constexpr int NA = (LA + 1) * (LA + 2) / 2, NB = (LB + 1) * (LB + 2) / 2;
-    constexpr int NC = (LC + 1) * (LC + 2) / 2, ND = (LD + 1) * (LD + 2) / 2;
-    constexpr int NF = NA * NB * NC * ND;
-    constexpr int R = 2 * (NA + NB);
-    constexpr bool kRegTile = NF <= 36;
-    // items are spread over the XCDs round-robin (item i on XCD i % 8, block
-    // b runs on XCD b % 8), so the density groups of one item share an L2
-    const int b = blockIdx.x;
-    const int xcd = b & 7, kk = b >> 3;
-    if (xcd >= a.nitems) return;
-    int lo = 0, hi = (a.nitems - 1 - xcd) >> 3;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.items[xcd + 8 * mid].kstart <= kk) lo = mid;
-        else hi = mid - 1;
-    }
-    const DigItem it = a.items[xcd + 8 * lo];
-    const int grp = kk - it.kstart;
-    if (grp < 0 || grp >= it.ngroups) return;
-    const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
-    const int G = it.G;
-    const int x0 = grp * G;
-    const int gn = min(G, m.nd - x0);
-    const int W = it.colAw + it.colBw;
-    const int nstrip = a.want_k ? R * G * W : 0;
-    const bool dstrip = a.want_k && it.dstrip;
-    double* __restrict__ strips = lds;                          // K strips [R][G][W]
-    double* __restrict__ dstr = lds + nstrip;                   // D strips [R][G][W] (dstrip)
-    double* __restrict__ jab = dstr + (dstrip ? nstrip : 0);    // [NA*NB][G]
-    const int nzero = nstrip;
-    for (int i = threadIdx.x; i < nzero; i += blockDim.x) lds[i] = 0.0;
-    if (a.want_j)
-        for (int i = threadIdx.x; i < NA * NB * G; i += blockDim.x) jab[i] = 0.0;
-
-    const int2 sg = it.seg;
-    const long long q0 = sg.x - it.chunk_q0;     // tile index of the segment's first quartet
-    const int slots = blockDim.x / G;
-    const int slot = threadIdx.x / G, g = threadIdx.x - slot * G;
-    const bool active = slot < slots && g < gn;
-    const int2* __restrict__ quartets = it.quartets + it.chunk_q0;
-    const PairInfo& P = m.pairs[quartets[q0].x];
-    const int fa = P.fa, fb = P.fb;
-    const long long nc = m.nc, ndp = m.nd, nq = it.chunk_n;
-    const int colA0 = it.colA0, colAw = it.colAw, colB0 = it.colB0;
-    auto lcol = [&](int col) { return (col >= colA0 && col < colA0 + colAw) ? col - colA0 : colAw + (col - colB0); };
-    if (dstrip) {
-        // D strips: rows of a and b, then columns of a and b, over the windows
-        for (int idx = threadIdx.x; idx < R * G * W; idx += blockDim.x) {
-            const int c = idx % W;
-            const int rg = idx / W;
-            const int gg = rg % G, r = rg / G;
-            const int col = c < colAw ? colA0 + c : colB0 + (c - colAw);
-            double v = 0.0;
-            if (gg < gn) {
-                const long long x = x0 + gg;
-                long long row, cl;
-                if (r < NA) { row = fa + r; cl = col; }
-                else if (r < NA + NB) { row = fb + r - NA; cl = col; }
-                else if (r < 2 * NA + NB) { row = col; cl = fa + r - NA - NB; }
-                else { row = col; cl = fb + r - 2 * NA - NB; }
-                v = m.D[(row * nc + cl) * ndp + x];
-            }
-            dstr[idx] = v;
-        }
-    }
-    __syncthreads();
-    double jacc[NA * NB];
-#pragma unroll
-    for (int e = 0; e < NA * NB; ++e) jacc[e] = 0.0;
-    if (active) {
-        const int x = x0 + g;
-        const double* __restrict__ Dm = m.D + x;
-        auto Dv = [&](int r, int c) -> double { return Dm[(r * nc + c) * ndp]; };
-        double* __restrict__ Jm = m.J + x;
-        double* __restrict__ sA = strips + static_cast<long long>(g) * W;   // row block 0, density g
-        auto S = [&](int row, int col) -> double* { return sA + static_cast<long long>(row) * G * W + col; };
-        const double* __restrict__ dA = dstr + static_cast<long long>(g) * W;
-        auto DKL = [&](int r, int lc, int, int) -> double { return dA[static_cast<long long>(r) * G * W + lc]; };
-        auto DKG = [&](int, int, int row, int col) -> double { return Dv(row, col); };
-        double s2ab[NA * NB];
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) s2ab[i * NB + j] = Dv(fa + i, fb + j) + Dv(fb + j, fa + i);
-#pragma unroll 1
-        for (int qi = slot; qi < sg.y; qi += slots) {
-            const long long q = q0 + qi;
-            const int2 bk = quartets[q];
-            const PairInfo& Q = m.pairs[bk.y];
-            if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) continue;
-            double w = 1.0;
-            if (P.sa == P.sb) w *= 0.5;
-            if (Q.sa == Q.sb) w *= 0.5;
-            if (bk.x == bk.y) w *= 0.5;
-            const TT* __restrict__ tg = static_cast<const TT*>(a.tiles) + it.tile_off + q;
-            double treg[kRegTile ? NF : 1];
-            if constexpr (kRegTile) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) treg[f] = static_cast<double>(tg[f * nq]);
-            }
-            auto I = [&](int i, int j, int k, int l) -> double {
-                const int f = ((i * NB + j) * NC + k) * ND + l;
-                if constexpr (kRegTile) return treg[f];
-                else return static_cast<double>(tg[static_cast<long long>(f) * nq]);
-            };
-            const int fc = Q.fa, fd = Q.fb;
-            const int cc = lcol(fc), cd = lcol(fd);
-            if (dstrip) {
-                if constexpr (kRegTile) {
-                    JK_DIGEST_QUARTET(_Pragma("unroll"), DKL)
-                } else {
-                    JK_DIGEST_QUARTET(_Pragma("unroll 1"), DKL)
-                }
-            } else {
-                if constexpr (kRegTile) {
-                    JK_DIGEST_QUARTET(_Pragma("unroll"), DKG)
-                } else {
-                    JK_DIGEST_QUARTET(_Pragma("unroll 1"), DKG)
-                }
-            }
-}
-        if (a.want_j) {
-#pragma unroll
-            for (int e = 0; e < NA * NB; ++e) atomicAdd(jab + e * G + g, jacc[e]);
-        }
-    }
-    __syncthreads();
-    // flush: column index fastest, so lanes write consecutive addresses
-    if (a.want_k) {
-        const long long mat = nc * nc;
-        for (int idx = threadIdx.x; idx < R * G * W; idx += blockDim.x) {
-            const int c = idx % W;
-            const int rg = idx / W;
-            const int gg = rg % G, r = rg / G;
-            if (gg >= gn) continue;
-            const double v = strips[idx];
-            if (v == 0.0) continue;
-            const int col = c < colAw ? colA0 + c : it.colB0 + (c - colAw);
-            const long long x = x0 + gg;
-            if (r < NA) unsafeAtomicAdd(m.K + x * mat + (fa + r) * nc + col, v);
-            else if (r < NA + NB) unsafeAtomicAdd(m.K + x * mat + (fb + r - NA) * nc + col, v);
-            else if (r < 2 * NA + NB) unsafeAtomicAdd(m.KT + x * mat + (fa + r - NA - NB) * nc + col, v);
-            else unsafeAtomicAdd(m.KT + x * mat + (fb + r - 2 * NA - NB) * nc + col, v);
-        }
-    }
-    if (a.want_j) {
-        for (int idx = threadIdx.x; idx < NA * NB * G; idx += blockDim.x) {
-            const int e = idx / G, gg = idx - e * G;
-            if (gg >= gn) continue;
-            const int i = e / NB, j = e - i * NB;
-            unsafeAtomicAdd(m.J + ((fa + i) * nc + fb + j) * ndp + x0 + gg, jab[idx]);
-        }
     }
 }
 

@@ -96,11 +96,11 @@ const double kSphD[5][6] = {
 int class_nf(int cls) { return kClassCost[cls].nfunc; }
 
 // Schedule tunables per class (process-wide; chosen by jk_autotune): the
-// length cap of a digestion segment (a run of quartets sharing a bra pair,
-// the unit of work of a digestion workgroup) and the cap on the densities a
-// digestion workgroup handles at once.
+// length cap of a digestion piece (quartets of one bra pair digested by one
+// wave) and the densities a digestion wave takes at once (16, or 8 when
+// g_max < 16 or the batch has at most 8 densities).
 struct Tune {
-    int seg_max = 1024;
+    int seg_max = 256;
     int g_max = 16;
 };
 std::mutex g_tune_mu;
@@ -114,15 +114,17 @@ Tune tune_of(int cls) {
 
 
 // A class list holds its FP64-tier quartets (Q_ab Q_cd >= fp32 bound) first
-// and its FP32-tier quartets after them; segments never straddle the two.
+// and its FP32-tier quartets after them.  Within a tier the quartets of one
+// bra pair are consecutive (a block) with ket pairs in (c, d) order.
 struct ClassList {
     long long count = 0;
     long long n64 = 0;               // quartets of the FP64 tier (list prefix)
-    int nseg64 = 0;                  // segments of the FP64 tier (prefix of segs)
+    int nblk64 = 0;                  // blocks of the FP64 tier (prefix of blocks)
     double prim_quartets[2] = {0, 0};   // sum of nprim_bra * nprim_ket per tier
     int2* dev = nullptr;
-    std::vector<int2> segs;          // (first quartet, count)
-    int2* dev_segs = nullptr;
+    std::vector<int2> blocks;        // (first quartet, count)
+    int* dev_pos = nullptr;          // per quartet: its position in the block's (d, c) order
+    int* dev_dord = nullptr;         // per (d, c) position: block offset of the quartet there
 };
 
 // pair class X -> (la, lb)
@@ -162,11 +164,8 @@ struct jk_basis_s {
     double list_bound = 1e-6;          // FP32-tier bound the lists are partitioned with
     float* d_boys32 = nullptr;
     ClassList lists[kNumClass];
-    std::vector<int2*> retired;
-    int lds_cap = 65536;               // dynamic LDS bytes per workgroup
-    int lw_off[kMaxL + 1] = {}, lw_len[kMaxL + 1] = {};   // Cartesian function window per l
+    std::vector<void*> retired;
     int list_gen = 0;                  // bumped whenever the lists are rebuilt
-    int tune_gen = -1;                 // tunables the lists were segmented with
     std::vector<CachedPlan*> plans;    // single-molecule plans (freed by jk_destroy)
     double stats[6] = {0, 0, 0, 0, 0, 0};
     // measurement: event pairs around integral / digestion launches
@@ -193,7 +192,8 @@ struct jk_basis_s {
         (void)hipFree(d_shell_nf);
         for (auto& l : lists) {
             (void)hipFree(l.dev);
-            (void)hipFree(l.dev_segs);
+            (void)hipFree(l.dev_pos);
+            (void)hipFree(l.dev_dord);
         }
         for (auto* p : retired) (void)hipFree(p);
         for (auto& r : prof) {
@@ -335,30 +335,43 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             }
             std::vector<int2> out(tier[0]);
             out.insert(out.end(), tier[1].begin(), tier[1].end());
-            fresh[cls].count = static_cast<long long>(out.size());
-            fresh[cls].n64 = static_cast<long long>(tier[0].size());
-            fresh[cls].prim_quartets[0] = primq[0];
-            fresh[cls].prim_quartets[1] = primq[1];
-            // segments: bra-pair runs of at most seg_max quartets, per tier
-            const int seg_max = tune_of(cls).seg_max;
-            auto& segs = fresh[cls].segs;
+            ClassList& F = fresh[cls];
+            F.count = static_cast<long long>(out.size());
+            F.n64 = static_cast<long long>(tier[0].size());
+            F.prim_quartets[0] = primq[0];
+            F.prim_quartets[1] = primq[1];
+            // blocks (one bra pair, one tier) and their (d, c) orders
+            std::vector<int> pos(out.size()), dord(out.size()), idx;
             for (int t = 0; t < 2; ++t) {
                 const size_t lo = t ? tier[0].size() : 0, hi = t ? out.size() : tier[0].size();
                 for (size_t q = lo; q < hi;) {
                     size_t e = q + 1;
-                    while (e < hi && out[e].x == out[q].x && static_cast<int>(e - q) < seg_max) ++e;
-                    segs.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
+                    while (e < hi && out[e].x == out[q].x) ++e;
+                    F.blocks.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
+                    idx.resize(e - q);
+                    for (size_t i = 0; i < idx.size(); ++i) idx[i] = static_cast<int>(i);
+                    std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
+                        const PairInfo& U = h->pairs[out[q + u].y];
+                        const PairInfo& V = h->pairs[out[q + v].y];
+                        return U.sb != V.sb ? U.sb < V.sb : U.sa < V.sa;
+                    });
+                    for (size_t p = 0; p < idx.size(); ++p) {
+                        dord[q + p] = idx[p];
+                        pos[q + idx[p]] = static_cast<int>(p);
+                    }
                     q = e;
                 }
-                if (t == 0) fresh[cls].nseg64 = static_cast<int>(segs.size());
+                if (t == 0) F.nblk64 = static_cast<int>(F.blocks.size());
             }
             if (!out.empty()) {
-                int rc = upload(&fresh[cls].dev, out);
-                if (!rc) rc = upload(&fresh[cls].dev_segs, segs);
+                int rc = upload(&F.dev, out);
+                if (!rc) rc = upload(&F.dev_pos, pos);
+                if (!rc) rc = upload(&F.dev_dord, dord);
                 if (rc) {
                     for (auto& f : fresh) {
                         (void)hipFree(f.dev);
-                        (void)hipFree(f.dev_segs);
+                        (void)hipFree(f.dev_pos);
+                        (void)hipFree(f.dev_dord);
                     }
                     return rc;
                 }
@@ -367,16 +380,13 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
     }
     for (int c = 0; c < kNumClass; ++c) {
         if (h->lists[c].dev) h->retired.push_back(h->lists[c].dev);
-        if (h->lists[c].dev_segs) h->retired.push_back(h->lists[c].dev_segs);
+        if (h->lists[c].dev_pos) h->retired.push_back(h->lists[c].dev_pos);
+        if (h->lists[c].dev_dord) h->retired.push_back(h->lists[c].dev_dord);
         h->lists[c] = fresh[c];
     }
     h->list_tol = tol;
     h->list_bound = bound;
     h->list_gen++;
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        h->tune_gen = g_tune_gen;
-    }
     return JK_OK;
 }
 
@@ -386,28 +396,22 @@ int ensure_lists(jk_basis_s* h, double tol, double bound) {
     std::lock_guard<std::mutex> g(h->mu);
     const bool tol_ok = h->list_tol >= 0 && h->list_tol <= tol;
     const bool bound_ok = bound < 0 || h->list_bound == bound;
-    int tg;
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        tg = g_tune_gen;
-    }
-    if (tol_ok && bound_ok && h->tune_gen == tg) return JK_OK;
+    if (tol_ok && bound_ok) return JK_OK;
     return build_lists(h, tol_ok ? h->list_tol : tol, bound < 0 ? h->list_bound : bound);
 }
 
 // ----------------------------------------------------------- work plans ---
 
-// One class and tier of a build: an integral launch over eri items and a
-// digestion launch over dig items, all molecules together.
+// One class and tier of a build: an integral launch over eri items and two
+// digestion launches (pass C, pass D) over dig items, all molecules together.
 struct LaunchRec {
-    int cls = 0, fp32 = 0;
+    int cls = 0, fp32 = 0, g16 = 1;
     int eri0 = 0, neri = 0;
     long long eri_blocks = 0;
-    int dig0 = 0, ndig = 0;
-    unsigned dig_blocks = 0;
-    size_t lds = 0;
+    int dig0[2] = {0, 0}, ndig[2] = {0, 0};
+    unsigned dig_blocks[2] = {0, 0};
     double eri_flops = 0, dig_flops = 0, quartets = 0, tile_bytes = 0;
-    int kcount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int kcount[2][8] = {};
 };
 
 struct MolRun {
@@ -417,42 +421,51 @@ struct MolRun {
 
 struct WorkPlan {
     std::vector<EriItem> eri;
-    std::vector<DigItem> dig;
+    std::vector<DigItem> dig[2];
     std::vector<LaunchRec> launches;
     long long tile_elems = 1296;
     double stats[6] = {0, 0, 0, 0, 0, 0};
 };
 
+// Density stride of a molecule with nd densities: a multiple of the
+// digestion group, 16 beyond 8 densities and 8 up to there.
+int dens_stride(int nd) { return nd > 8 ? (nd + 15) / 16 * 16 : 8; }
+
 // Split every class list (per tier) of every molecule into tile items of
-// whole segments and digestion items (one per segment), packing items into
-// launches whose tiles fit a buffer of cap elements.
-int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_cap, long long cap, WorkPlan& wp) {
+// whole blocks and digestion pieces (pass C in list order, pass D in (d, c)
+// order), packing items into launches whose tiles fit a buffer of cap
+// elements.
+int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long cap, WorkPlan& wp) {
     const bool mixed = o->precision == JK_MIXED;
+    bool all16 = true;
+    for (const MolRun& r : mols) all16 = all16 && dens_stride(r.nd) % 16 == 0;
     for (int c = 0; c < kNumClass; ++c) {
         const int NF = class_nf(c);
-        int X = 0;
-        while (X + 1 < kNumPairClass && quartet_class(X + 1, 0) <= c) ++X;
-        const int Y = c - quartet_class(X, 0);
-        const int la = kPairL[X][0], lb = kPairL[X][1], lc = kPairL[Y][0], ld = kPairL[Y][1];
-        const int NA = ncart(la), NB = ncart(lb);
+        const int wpb = dig_wpb(NF);
+        const Tune tn = tune_of(c);
+        const int g16 = all16 && tn.g_max >= 16;
+        const int G = g16 ? 16 : 8;
+        const int piece = std::max(1, tn.seg_max);
         for (int tier = 0; tier < (mixed ? 2 : 1); ++tier) {
             const int fp32 = mixed && tier == 1;
             LaunchRec L;
-            L.cls = c;
-            L.fp32 = fp32;
             long long used = 0;
             auto flush = [&]() {
                 if (L.neri > 0) {
-                    int kmax = 0;
-                    for (int x = 0; x < 8; ++x) kmax = std::max(kmax, L.kcount[x]);
-                    L.dig_blocks = static_cast<unsigned>(8 * kmax);
+                    for (int ps = 0; ps < 2; ++ps) {
+                        int kmax = 0;
+                        for (int x = 0; x < 8; ++x) kmax = std::max(kmax, L.kcount[ps][x]);
+                        L.dig_blocks[ps] = static_cast<unsigned>(8 * ((kmax + wpb - 1) / wpb));
+                    }
                     wp.launches.push_back(L);
                 }
                 LaunchRec fresh;
                 fresh.cls = c;
                 fresh.fp32 = fp32;
+                fresh.g16 = g16;
                 fresh.eri0 = static_cast<int>(wp.eri.size());
-                fresh.dig0 = static_cast<int>(wp.dig.size());
+                fresh.dig0[0] = static_cast<int>(wp.dig[0].size());
+                fresh.dig0[1] = static_cast<int>(wp.dig[1].size());
                 L = fresh;
                 used = 0;
             };
@@ -462,38 +475,25 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_c
                 const int nd = mols[mi].nd;
                 const ClassList& CL = h->lists[c];
                 if (CL.count == 0) continue;
-                const int nseg = static_cast<int>(CL.segs.size());
-                const int sbeg = tier ? CL.nseg64 : 0, send = (tier || !mixed) ? nseg : CL.nseg64;
-                if (sbeg >= send) continue;
+                const int nblk = static_cast<int>(CL.blocks.size());
+                const int bbeg = tier ? CL.nblk64 : 0, bend = (tier || !mixed) ? nblk : CL.nblk64;
+                if (bbeg >= bend) continue;
                 const long long nq_tier = mixed ? (tier ? CL.count - CL.n64 : CL.n64) : CL.count;
                 const double prim_tier = mixed ? CL.prim_quartets[tier] : CL.prim_quartets[0] + CL.prim_quartets[1];
                 const double prim_avg = prim_tier / static_cast<double>(std::max<long long>(nq_tier, 1));
-                const int colA0 = h->lw_off[lc], colAw = h->lw_len[lc];
-                const int colB0 = ld != lc ? h->lw_off[ld] : 0, colBw = ld != lc ? h->lw_len[ld] : 0;
-                const size_t strip = sizeof(double) * (o->want_k ? 2 * (NA + NB) * (colAw + colBw) : 0);
-                const size_t jpart = sizeof(double) * (o->want_j ? NA * NB : 0);
-                if (strip + jpart > static_cast<size_t>(lds_cap))
-                    return fail(JK_EUNSUPPORTED, "class %d of a %d-function basis needs %zu bytes of LDS per density "
-                                "(limit %d)", c, h->nc, strip + jpart, lds_cap);
-                // stage the density strips in LDS as well when they fit
-                const int dstrip = o->want_k && 2 * strip + jpart <= static_cast<size_t>(lds_cap);
-                const size_t per_density = (dstrip ? 2 * strip : strip) + jpart;
-                int G = 16;
-                const int gmax = tune_of(c).g_max;
-                while (G > 1 && (G > gmax || G / 2 >= nd || G * per_density > static_cast<size_t>(lds_cap))) G /= 2;
-                const int ngroups = (nd + G - 1) / G;
-                for (int s0 = sbeg; s0 < send;) {
-                    const long long q0 = CL.segs[s0].x;
-                    int s1 = s0;
-                    while (s1 < send && (CL.segs[s1].x + CL.segs[s1].y - q0) * NF <= cap - used) ++s1;
-                    if (s1 == s0) {
+                const int ngroups = dens_stride(nd) / G;
+                for (int b0 = bbeg; b0 < bend;) {
+                    const long long q0 = CL.blocks[b0].x;
+                    int b1 = b0;
+                    while (b1 < bend && (CL.blocks[b1].x + CL.blocks[b1].y - q0) * NF <= cap - used) ++b1;
+                    if (b1 == b0) {
                         if (used > 0) {
                             flush();
                             continue;
                         }
-                        return fail(JK_EDEVICE, "internal: a segment exceeds the work buffer");
+                        return fail(JK_EDEVICE, "internal: a bra-pair block exceeds the work buffer");
                     }
-                    const long long n = CL.segs[s1 - 1].x + CL.segs[s1 - 1].y - q0;
+                    const long long n = CL.blocks[b1 - 1].x + CL.blocks[b1 - 1].y - q0;
                     EriItem e{};
                     e.quartets = CL.dev + q0;
                     e.n = n;
@@ -503,28 +503,28 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_c
                     wp.eri.push_back(e);
                     L.neri++;
                     L.eri_blocks += (n + 255) / 256;
-                    for (int k = s0; k < s1; ++k) {
-                        DigItem d{};
-                        d.quartets = CL.dev;
-                        d.seg = CL.segs[k];
-                        d.chunk_q0 = q0;
-                        d.chunk_n = n;
-                        d.tile_off = used;
-                        d.mol = static_cast<int>(mi);
-                        d.G = G;
-                        d.ngroups = ngroups;
-                        const int x = L.ndig % 8;
-                        d.kstart = L.kcount[x];
-                        L.kcount[x] += ngroups;
-                        d.colA0 = colA0;
-                        d.colAw = colAw;
-                        d.colB0 = colB0;
-                        d.colBw = colBw;
-                        d.dstrip = dstrip;
-                        wp.dig.push_back(d);
-                        L.ndig++;
+                    for (int k = b0; k < b1; ++k) {
+                        for (int ps = 0; ps < (o->want_k ? 2 : 1); ++ps) {
+                            for (int p0 = 0; p0 < CL.blocks[k].y; p0 += piece) {
+                                DigItem d{};
+                                d.quartets = CL.dev;
+                                d.order = ps ? CL.dev_dord : CL.dev_pos;
+                                d.blk0 = CL.blocks[k].x;
+                                d.chunk_q0 = q0;
+                                d.chunk_n = n;
+                                d.tile_off = used;
+                                d.p0 = p0;
+                                d.plen = std::min(piece, CL.blocks[k].y - p0);
+                                d.mol = static_cast<int>(mi);
+                                d.ngroups = ngroups;
+                                const int x = L.ndig[ps] % 8;
+                                d.kstart = L.kcount[ps][x];
+                                L.kcount[ps][x] += ngroups;
+                                wp.dig[ps].push_back(d);
+                                L.ndig[ps]++;
+                            }
+                        }
                     }
-                    L.lds = std::max(L.lds, G * per_density);
                     const double ef = n * (prim_avg * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
                                            kClassCost[c].hrr_flops);
                     const double df = static_cast<double>(n) * NF * nd *
@@ -541,7 +541,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, int lds_c
                     wp.stats[5] += df;
                     used += n * NF;
                     wp.tile_elems = std::max(wp.tile_elems, used);
-                    s0 = s1;
+                    b0 = b1;
                 }
             }
             flush();
@@ -559,7 +559,7 @@ inline size_t al256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     MolSpace m{};
-    const size_t mat = static_cast<size_t>(h->nc) * h->nc * nd * sizeof(double);
+    const size_t mat = static_cast<size_t>(h->nc) * h->nc * dens_stride(nd) * sizeof(double);
     size_t off = 0;
     m.off_D = off;
     off += al256(mat);
@@ -577,10 +577,10 @@ MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
 
 // A cached plan of a single-molecule build, with its items on the device.
 struct CachedPlan {
-    int nd, mixed, want_j, want_k, gen;
+    int nd, mixed, want_j, want_k, gen, tgen;
     WorkPlan wp;
     EriItem* d_eri = nullptr;
-    DigItem* d_dig = nullptr;
+    DigItem* d_dig[2] = {nullptr, nullptr};
 };
 
 bool valid_opts(const jk_build_opts* o) {
@@ -699,20 +699,6 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     }
     h->f0_int[ns] = fc;
     h->nc = fc;
-    for (int l = kMaxL; l >= 0; --l) {
-        h->lw_off[l] = fc;
-        h->lw_len[l] = 0;
-    }
-    for (int si = ns - 1; si >= 0; --si) {
-        const int l = h->l_int[si];
-        h->lw_off[l] = h->f0_int[si];
-        h->lw_len[l] += ncart(l);
-    }
-    {
-        int cap = 0;
-        HIPC(hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-        h->lds_cap = cap > 0 ? cap : 65536;
-    }
 
     // shell pairs (a >= b internal, la >= lb) and primitive pairs
     h->pair_id.assign(static_cast<size_t>(ns) * ns, -1);
@@ -844,26 +830,13 @@ int jk_last_stats(jk_basis_t h, double out[6]) {
 
 namespace {
 
-std::mutex g_prep_mu;
-size_t g_prepared[kNumClass] = {};   // dynamic LDS granted per digestion kernel
-
-hipError_t prepare_lds(int cls, size_t bytes) {
-    std::lock_guard<std::mutex> g(g_prep_mu);
-    if (g_prepared[cls] >= bytes) return hipSuccess;
-    hipError_t e = digest_prepare(cls, bytes);
-    if (e == hipSuccess) g_prepared[cls] = bytes;
-    return e;
-}
-
 // Launch every class/tier of a plan on stream s.  prof: handle that records
 // per-kernel events when profiling is on (single-molecule builds).
-hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, const DigItem* d_dig, const MolDesc& mol0,
+hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_dig[2], const MolDesc& mol0,
                     const MolDesc* d_mols, void* tiles, void* scratch, const jk_build_opts* o, const double* boys,
                     const float* boys32, hipStream_t s, jk_basis_s* prof) {
     hipError_t e = hipSuccess;
     for (const LaunchRec& L : wp.launches) {
-        e = prepare_lds(L.cls, L.lds);
-        if (e != hipSuccess) return e;
         EriTileArgs ea{};
         ea.items = d_eri + L.eri0;
         ea.nitems = L.neri;
@@ -875,17 +848,18 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, const DigItem* d_d
         ea.tol = o->schwarz_tol;
         ea.tiles = tiles;
         ea.scratch = scratch;
-        DigestArgs da{};
-        da.items = d_dig + L.dig0;
-        da.nitems = L.ndig;
-        da.mol0 = mol0;
-        da.mols = d_mols;
-        da.tol = o->schwarz_tol;
-        da.tiles = tiles;
-        da.want_j = o->want_j;
-        da.want_k = o->want_k;
-        da.lds_bytes = L.lds;
-        da.nblocks = L.dig_blocks;
+        DigestArgs da[2]{};
+        for (int ps = 0; ps < 2; ++ps) {
+            da[ps].items = d_dig[ps] + L.dig0[ps];
+            da[ps].nitems = L.ndig[ps];
+            da[ps].mol0 = mol0;
+            da[ps].mols = d_mols;
+            da[ps].tiles = tiles;
+            da[ps].dcopy = scratch;
+            da[ps].want_j = o->want_j;
+            da[ps].want_k = o->want_k;
+            da[ps].nblocks = L.ndig[ps] > 0 ? L.dig_blocks[ps] : 0;
+        }
         const bool timed = prof && prof->profiling;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         if (timed) {
@@ -896,7 +870,8 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, const DigItem* d_d
         }
         e = launch_eri_tile(L.cls, ea, s, L.fp32);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
-        if (e == hipSuccess) e = launch_digest(L.cls, da, s, L.fp32);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[0], s, L.fp32, 0, L.g16);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[2], s);
         if (e != hipSuccess) return e;
         if (timed) {
@@ -911,17 +886,23 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, const DigItem* d_d
 void free_plan(CachedPlan* cp) {
     if (!cp) return;
     (void)hipFree(cp->d_eri);
-    (void)hipFree(cp->d_dig);
+    (void)hipFree(cp->d_dig[0]);
+    (void)hipFree(cp->d_dig[1]);
     delete cp;
 }
 
 // The cached plan of a single-molecule build (created on first use).
 int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
     const int mixed = o->precision == JK_MIXED;
+    int tgen;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tgen = g_tune_gen;
+    }
     std::lock_guard<std::mutex> g(h->mu);
     for (CachedPlan* cp : h->plans)
         if (cp->nd == nd && cp->mixed == mixed && cp->want_j == o->want_j && cp->want_k == o->want_k &&
-            cp->gen == h->list_gen) {
+            cp->gen == h->list_gen && cp->tgen == tgen) {
             *out = cp;
             return JK_OK;
         }
@@ -931,9 +912,11 @@ int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
     cp->want_j = o->want_j;
     cp->want_k = o->want_k;
     cp->gen = h->list_gen;
-    int rc = plan_work({MolRun{h, nd}}, o, h->lds_cap, kTileCapElems, cp->wp);
+    cp->tgen = tgen;
+    int rc = plan_work({MolRun{h, nd}}, o, kTileCapElems, cp->wp);
     if (!rc) rc = upload(&cp->d_eri, cp->wp.eri);
-    if (!rc) rc = upload(&cp->d_dig, cp->wp.dig);
+    if (!rc) rc = upload(&cp->d_dig[0], cp->wp.dig[0]);
+    if (!rc) rc = upload(&cp->d_dig[1], cp->wp.dig[1]);
     if (rc) {
         free_plan(cp);
         return rc;
@@ -952,9 +935,10 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     double* Kc = o->want_k ? reinterpret_cast<double*>(base + ms.off_K) : nullptr;
     double* KTc = o->want_k ? reinterpret_cast<double*>(base + ms.off_KT) : nullptr;
     double* dmax = reinterpret_cast<double*>(base + ms.off_dmax);
-    const long long mat = static_cast<long long>(h->nc) * h->nc * nd;
-    hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, nd, Dc, s);
-    if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, nd, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
+    const int ndp = dens_stride(nd);
+    const long long mat = static_cast<long long>(h->nc) * h->nc * ndp;
+    hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, ndp, Dc, s);
+    if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
     if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
     if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
     if (e == hipSuccess && KTc) e = launch_zero(KTc, mat, s);
@@ -968,11 +952,12 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     md.ns = h->ns;
     md.nc = h->nc;
     md.nd = nd;
+    md.ndp = ndp;
     return e;
 }
 
 hipError_t mol_post(const jk_basis_s* h, int nd, const MolDesc& md, double* J, double* K, hipStream_t s) {
-    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, nd, J, K, s);
+    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, md.ndp, J, K, s);
 }
 
 int check_opts(const char* who, const jk_build_opts* o) {
@@ -1088,23 +1073,21 @@ struct BatchSetup {
     std::vector<MolSpace> ms;
     std::vector<size_t> mol_off;
     size_t off_tiles = 0, off_scr = 0, off_items = 0, total = 0;
-    size_t eri_bytes = 0, dig_bytes = 0, mol_bytes = 0;
+    size_t eri_bytes = 0, dig_bytes[2] = {0, 0}, mol_bytes = 0;
 };
 
 int batch_setup(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const jk_build_opts* o, BatchSetup& b) {
     if (nmol < 1 || !hs || !nd) return fail(JK_EINVAL, "jk_build_batch: nmol >= 1 and non-NULL arrays required");
     const int mixed = o->precision == JK_MIXED;
-    int lds_cap = 1 << 30;
     for (int i = 0; i < nmol; ++i) {
         if (!hs[i]) return fail(JK_EINVAL, "jk_build_batch: handle %d is NULL", i);
         if (nd[i] < 1) return fail(JK_EINVAL, "jk_build_batch: nd[%d]=%d must be >= 1", i, nd[i]);
         if (hs[i]->device != hs[0]->device) return fail(JK_EINVAL, "jk_build_batch: handles on different devices");
         int rc = ensure_lists(hs[i], o->schwarz_tol, mixed ? o->fp32_bound : -1.0);
         if (rc) return rc;
-        lds_cap = std::min(lds_cap, hs[i]->lds_cap);
         b.runs.push_back(MolRun{hs[i], nd[i]});
     }
-    int rc = plan_work(b.runs, o, lds_cap, kTileCapElems, b.wp);
+    int rc = plan_work(b.runs, o, kTileCapElems, b.wp);
     if (rc) return rc;
     size_t off = 0;
     for (int i = 0; i < nmol; ++i) {
@@ -1119,9 +1102,10 @@ int batch_setup(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const jk_
     off += tb;
     b.off_items = off;
     b.eri_bytes = al256(std::max<size_t>(1, b.wp.eri.size()) * sizeof(EriItem));
-    b.dig_bytes = al256(std::max<size_t>(1, b.wp.dig.size()) * sizeof(DigItem));
+    b.dig_bytes[0] = al256(std::max<size_t>(1, b.wp.dig[0].size()) * sizeof(DigItem));
+    b.dig_bytes[1] = al256(std::max<size_t>(1, b.wp.dig[1].size()) * sizeof(DigItem));
     b.mol_bytes = al256(nmol * sizeof(MolDesc));
-    off += b.eri_bytes + b.dig_bytes + b.mol_bytes;
+    off += b.eri_bytes + b.dig_bytes[0] + b.dig_bytes[1] + b.mol_bytes;
     b.total = off;
     return JK_OK;
 }
@@ -1185,15 +1169,18 @@ int jk_build_batch(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const 
         e = mol_pre(hs[i], nd[i], D[i], o, ws + b.mol_off[i], b.ms[i], mds[i], s);
     // work items and molecule table, staged through host memory the stream frees
     EriItem* d_eri = reinterpret_cast<EriItem*>(ws + b.off_items);
-    DigItem* d_dig = reinterpret_cast<DigItem*>(ws + b.off_items + b.eri_bytes);
-    MolDesc* d_mols = reinterpret_cast<MolDesc*>(ws + b.off_items + b.eri_bytes + b.dig_bytes);
-    const size_t host_bytes = b.eri_bytes + b.dig_bytes + b.mol_bytes;
+    DigItem* const d_dig[2] = {reinterpret_cast<DigItem*>(ws + b.off_items + b.eri_bytes),
+                               reinterpret_cast<DigItem*>(ws + b.off_items + b.eri_bytes + b.dig_bytes[0])};
+    const size_t mol_at = b.eri_bytes + b.dig_bytes[0] + b.dig_bytes[1];
+    MolDesc* d_mols = reinterpret_cast<MolDesc*>(ws + b.off_items + mol_at);
+    const size_t host_bytes = mol_at + b.mol_bytes;
     char* stage = static_cast<char*>(std::malloc(host_bytes));
     if (!stage) e = hipErrorOutOfMemory;
     if (e == hipSuccess) {
         std::memcpy(stage, b.wp.eri.data(), b.wp.eri.size() * sizeof(EriItem));
-        std::memcpy(stage + b.eri_bytes, b.wp.dig.data(), b.wp.dig.size() * sizeof(DigItem));
-        std::memcpy(stage + b.eri_bytes + b.dig_bytes, mds.data(), nmol * sizeof(MolDesc));
+        std::memcpy(stage + b.eri_bytes, b.wp.dig[0].data(), b.wp.dig[0].size() * sizeof(DigItem));
+        std::memcpy(stage + b.eri_bytes + b.dig_bytes[0], b.wp.dig[1].data(), b.wp.dig[1].size() * sizeof(DigItem));
+        std::memcpy(stage + mol_at, mds.data(), nmol * sizeof(MolDesc));
         e = hipMemcpyAsync(ws + b.off_items, stage, host_bytes, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipLaunchHostFunc(s, free_host_cb, stage);
         else std::free(stage);
@@ -1268,8 +1255,8 @@ int jk_tune_load(const char* path) {
 int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o,
                 const char* cache_path) {
     if (!h || !o || nd < 1 || !D || !J || !K) return fail(JK_EINVAL, "jk_autotune: bad arguments");
-    static const int kSeg[] = {128, 256, 512, 1024, 2048};
-    static const int kG[] = {4, 8, 16};
+    static const int kSeg[] = {64, 128, 256, 512, 1024};
+    static const int kG[] = {8, 16};
     double best_ms[kNumClass];
     Tune best[kNumClass];
     for (int c = 0; c < kNumClass; ++c) best_ms[c] = 1e300;
@@ -1337,8 +1324,6 @@ int jk_graph_create(jk_basis_t h, int32_t nd, const double* D, double* J, double
     {
         CachedPlan* cp = nullptr;
         if ((rc = get_plan(h, nd, o, &cp))) return rc;
-        for (const LaunchRec& L : cp->wp.launches)
-            if (prepare_lds(L.cls, L.lds) != hipSuccess) return fail(JK_EDEVICE, "jk_graph_create: LDS attribute");
     }
     hipStream_t cs = nullptr;
     HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

@@ -6,10 +6,10 @@
 //   eri_tile   one lane per canonical shell quartet of one class: primitive
 //              loop -> Boys -> HGP-OS vertical recurrence -> contraction ->
 //              horizontal recurrences -> Cartesian tile to a work buffer
-//   digest     one lane per (quartet, density): J and K scatter of the tile
-//              with the canonical-fold multiplicity (Sect. 3, Eq.
-//              (quartet_scatter)), FP64 atomics into [i][j][x] accumulators
-//   cart2sph   J = T^T (Jc + Jc^T) T, K = T^T Kc T back to [x][m][n]
+//   digest     tiles against stacked densities on the FP64 matrix cores
+//              (jk_digest.h), two passes, FP64 atomics into [i][j][x]
+//              accumulators
+//   cart2sph   J = T^T (Jc + Jc^T) T, K = T^T (Kc + KTc^T) T back to [x][m][n]
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,8 +40,9 @@ __global__ void k_sph2cart(const double* __restrict__ D, int nd, int nf, const C
     }
 }
 
-// J[x][m][n] = sum T[i][m] (Jc[i][j][x] + Jc[j][i][x]) T[j][n] with Jc density-innermost;
-// K[x][m][n] = sum T[i][m] (Kc[x][i][j] + KTc[x][j][i]) T[j][n].
+// J[x][m][n] = sum T[i][m] (Jc[i][j][x] + Jc[j][i][x]) T[j][n] and
+// K[x][m][n] = sum T[i][m] (Kc[i][j][x] + KTc[j][i][x]) T[j][n], accumulators
+// density-innermost with stride ndp.
 __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restrict__ Kc,
                            const double* __restrict__ KTc, int nd, int nf, const UserMap* __restrict__ umap,
                            int nc, int ndp, double* __restrict__ J, double* __restrict__ K) {
@@ -57,9 +58,7 @@ __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restri
                 const long long ij = (static_cast<long long>(um.idx[u]) * nc + un.idx[v]) * ndp + x;
                 const long long ji = (static_cast<long long>(un.idx[v]) * nc + um.idx[u]) * ndp + x;
                 if (J) sj = fma(c, Jc[ij] + Jc[ji], sj);
-                const long long kij = (static_cast<long long>(x) * nc + um.idx[u]) * nc + un.idx[v];
-                const long long kji = (static_cast<long long>(x) * nc + un.idx[v]) * nc + um.idx[u];
-                if (K) sk = fma(c, Kc[kij] + KTc[kji], sk);
+                if (K) sk = fma(c, Kc[ij] + KTc[ji], sk);
             }
         if (J) J[static_cast<long long>(x) * nf * nf + t] = sj;
         if (K) K[static_cast<long long>(x) * nf * nf + t] = sk;
@@ -103,11 +102,11 @@ hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s, int fp3
     }
 }
 
-hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32) {
+hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16) {
     if (a.nblocks == 0) return hipSuccess;
     switch (cls) {
 #define JK_CASE(n) \
-    case n: return launch_digest_c##n(a, s, fp32);
+    case n: return launch_digest_c##n(a, s, fp32, pass, g16);
         JK_FOR_CLASS_INDEX(JK_CASE)
 #undef JK_CASE
         default: return hipErrorInvalidValue;
@@ -127,16 +126,6 @@ hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc
     hipLaunchKernelGGL(k_cart2sph, dim3(blocks_for(n, 256)), dim3(256), 0, s, Jc, Kc, KTc, nd, nf, umap, nc, ndp,
                        J, K);
     return hipGetLastError();
-}
-
-hipError_t digest_prepare(int cls, size_t lds_bytes) {
-    switch (cls) {
-#define JK_CASE(n) \
-    case n: return digest_prepare_c##n(lds_bytes);
-        JK_FOR_CLASS_INDEX(JK_CASE)
-#undef JK_CASE
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,

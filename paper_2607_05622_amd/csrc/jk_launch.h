@@ -24,16 +24,18 @@ struct UserMap {
     double c[3];
 };
 
-// Everything a kernel needs to know about one molecule of a launch.
+// Everything a kernel needs to know about one molecule of a launch.  The
+// density-indexed matrices are density-innermost, [nc][nc][ndp], with ndp
+// the density count rounded up to the digestion group (zero beyond nd).
 struct MolDesc {
     const PairInfo* pairs;
     const PrimPair* prims;
     const double* dmax;     // [ns][ns] or nullptr (no density screen)
-    const double* D;        // [nc][nc][nd]
-    double* J;              // [nc][nc][nd]
-    double* K;              // [nd][nc][nc], row-strip contributions
-    double* KT;             // [nd][nc][nc], column-strip contributions, transposed
-    int ns, nc, nd, pad;
+    const double* D;        // Cartesian densities
+    double* J;              // Coulomb accumulator (J = Jc + Jc^T at the end)
+    double* K;              // exchange, row contributions K[a][c]
+    double* KT;             // exchange, transposed contributions (K += KT^T at the end)
+    int ns, nc, nd, ndp;
 };
 
 // A contiguous run of one molecule's class list whose tiles occupy
@@ -59,17 +61,21 @@ struct EriTileArgs {
     void* scratch;          // (e0|cd) of pass-evaluated classes, same offsets as tiles
 };
 
-// One digestion unit: a run of quartets sharing the bra pair, digested by
-// ngroups workgroups of G densities each.
+// One digestion unit: a piece of the quartets of one bra pair (a "block":
+// the bra pair's quartets of one class and tier, consecutive in the class
+// list with ket pairs in (c, d) order), digested by ngroups waves of 8 or
+// 16 densities each.  Pass C walks the block in list order (runs of equal
+// ket shell c), pass D in the order sorted by (d, c) (runs of equal d).
 struct DigItem {
     const int2* quartets;   // the molecule's class list
-    int2 seg;               // (first quartet in the class list, count)
-    long long chunk_q0;     // class-list index of the first quartet of the seg's tile item
+    const int* order;       // pass C: D-order position of each list quartet within its block;
+                            // pass D: block offset of the quartet at each D-order position
+    long long blk0;         // class-list index of the block's first quartet
+    long long chunk_q0;     // class-list index of the first quartet of the block's tile item
     long long chunk_n;      // tile stride of that item
-    long long tile_off;     // element offset of that item's tiles
-    int mol, G, ngroups, kstart;   // kstart: first block index within this item's XCD
-    int colA0, colAw, colB0, colBw;   // LDS column windows (ket shells' functions)
-    int dstrip, pad;                  // 1: density strips staged in LDS too
+    long long tile_off;     // element offset of that item's tiles (and of its D-order copy)
+    int p0, plen;           // the piece: positions [p0, p0 + plen) in this pass's order
+    int mol, ngroups, kstart, pad;   // kstart: first wave task of the item on its XCD
 };
 
 struct DigestArgs {
@@ -77,11 +83,10 @@ struct DigestArgs {
     int nitems;
     MolDesc mol0;
     const MolDesc* mols;
-    double tol;
-    const void* tiles;
+    const void* tiles;      // [NF][n] per tile item, double or float
+    void* dcopy;            // D-order copy [n][NF] per tile item, written by pass C
     int want_j, want_k;
-    size_t lds_bytes;       // dynamic LDS of the launch (largest item)
-    unsigned nblocks;       // 8 x the largest per-XCD block count
+    unsigned nblocks;       // 8 x the largest per-XCD workgroup count
 };
 
 // one launcher pair per canonical class index, defined in jk_class.hip
@@ -89,16 +94,15 @@ struct DigestArgs {
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 #define JK_DECLARE(n)                                                                 \
     hipError_t launch_eri_tile_c##n(const EriTileArgs& a, hipStream_t s, int fp32); \
-    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s, int fp32);    \
-    hipError_t digest_prepare_c##n(size_t lds_bytes);
+    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16);
 JK_FOR_CLASS_INDEX(JK_DECLARE)
 #undef JK_DECLARE
 
 // fp32 = 1: the FP32 tier (float recurrences and tiles)
 hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s, int fp32 = 0);
-hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32 = 0);
-// Allow the digestion kernels of class cls up to lds_bytes of dynamic LDS.
-hipError_t digest_prepare(int cls, size_t lds_bytes);
+// pass 0: C-order digestion (J, K rows/columns of c), pass 1: D-order (K of d);
+// g16 = 1: 16 densities per wave task, 0: 8
+hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16);
 hipError_t launch_sph2cart(const double* D, int nd, int nf, const CartMap* cmap, int nc, int ndp, double* Dc,
                            hipStream_t s);
 hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc, int nd, int nf,
