@@ -91,7 +91,8 @@ void jk_default_opts(jk_build_opts* o);
  * factors and screened quartet lists.  Synchronous.  On success *out owns
  * device memory until jk_destroy.  JK_EINVAL for an invalid descriptor
  * (l > JK_MAX_L, nprim outside 1..JK_MAX_PRIM, exponent <= 0 or non-finite,
- * NULL arrays, shell_atom out of range). */
+ * NULL arrays, shell_atom out of range); JK_EUNSUPPORTED for more than
+ * 65535 Cartesian functions. */
 int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out);
 
 /* Number of basis functions n of the D/J/K matrices (pure or Cartesian). */

@@ -23,16 +23,17 @@ hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Digestion: one workgroup per task; pass C has a J wave and one K wave per
+// density form, pass D one K wave per density form.
 template <int la, int lb, int lc, int ld, typename TT>
 hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16) {
-    constexpr int wpb = DigShape<la, lb, lc, ld>::WPB;
-    const dim3 grid(a.nblocks), block(64 * wpb);
+    const dim3 grid(a.nblocks);
     if (pass == 0) {
-        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(192), 0, s, a);
+        else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, dim3(128), 0, s, a);
     } else {
-        if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+        if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, false>), grid, dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

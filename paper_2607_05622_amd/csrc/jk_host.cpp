@@ -100,7 +100,7 @@ int class_nf(int cls) { return kClassCost[cls].nfunc; }
 // wave) and the densities a digestion wave takes at once (16, or 8 when
 // g_max < 16 or the batch has at most 8 densities).
 struct Tune {
-    int seg_max = 256;
+    int seg_max = 32;
     int g_max = 16;
 };
 std::mutex g_tune_mu;
@@ -123,8 +123,10 @@ struct ClassList {
     double prim_quartets[2] = {0, 0};   // sum of nprim_bra * nprim_ket per tier
     int2* dev = nullptr;
     std::vector<int2> blocks;        // (first quartet, count)
+    std::vector<int> block_bra;      // bra shell pair of each block
     int* dev_pos = nullptr;          // per quartet: its position in the block's (d, c) order
-    int* dev_dord = nullptr;         // per (d, c) position: block offset of the quartet there
+    int2* dev_kin = nullptr;         // per quartet, list order: (c | d << 16, fc | fd << 16) of the ket
+    int2* dev_kind = nullptr;        // the same per position of the blocks' (d, c) orders
 };
 
 // pair class X -> (la, lb)
@@ -193,7 +195,8 @@ struct jk_basis_s {
         for (auto& l : lists) {
             (void)hipFree(l.dev);
             (void)hipFree(l.dev_pos);
-            (void)hipFree(l.dev_dord);
+            (void)hipFree(l.dev_kin);
+            (void)hipFree(l.dev_kind);
         }
         for (auto* p : retired) (void)hipFree(p);
         for (auto& r : prof) {
@@ -340,14 +343,21 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             F.n64 = static_cast<long long>(tier[0].size());
             F.prim_quartets[0] = primq[0];
             F.prim_quartets[1] = primq[1];
-            // blocks (one bra pair, one tier) and their (d, c) orders
-            std::vector<int> pos(out.size()), dord(out.size()), idx;
+            // blocks (one bra pair, one tier), their (d, c) orders and the
+            // ket shells and functions the digestion reads per position
+            std::vector<int> pos(out.size()), idx;
+            std::vector<int2> kin(out.size()), kind(out.size());
+            for (size_t q = 0; q < out.size(); ++q) {
+                const PairInfo& Q = h->pairs[out[q].y];
+                kin[q] = make_int2(Q.sa | (Q.sb << 16), Q.fa | (Q.fb << 16));
+            }
             for (int t = 0; t < 2; ++t) {
                 const size_t lo = t ? tier[0].size() : 0, hi = t ? out.size() : tier[0].size();
                 for (size_t q = lo; q < hi;) {
                     size_t e = q + 1;
                     while (e < hi && out[e].x == out[q].x) ++e;
                     F.blocks.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
+                    F.block_bra.push_back(out[q].x);
                     idx.resize(e - q);
                     for (size_t i = 0; i < idx.size(); ++i) idx[i] = static_cast<int>(i);
                     std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
@@ -356,7 +366,7 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                         return U.sb != V.sb ? U.sb < V.sb : U.sa < V.sa;
                     });
                     for (size_t p = 0; p < idx.size(); ++p) {
-                        dord[q + p] = idx[p];
+                        kind[q + p] = kin[q + idx[p]];
                         pos[q + idx[p]] = static_cast<int>(p);
                     }
                     q = e;
@@ -366,12 +376,14 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             if (!out.empty()) {
                 int rc = upload(&F.dev, out);
                 if (!rc) rc = upload(&F.dev_pos, pos);
-                if (!rc) rc = upload(&F.dev_dord, dord);
+                if (!rc) rc = upload(&F.dev_kin, kin);
+                if (!rc) rc = upload(&F.dev_kind, kind);
                 if (rc) {
                     for (auto& f : fresh) {
                         (void)hipFree(f.dev);
                         (void)hipFree(f.dev_pos);
-                        (void)hipFree(f.dev_dord);
+                        (void)hipFree(f.dev_kin);
+                        (void)hipFree(f.dev_kind);
                     }
                     return rc;
                 }
@@ -381,7 +393,8 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
     for (int c = 0; c < kNumClass; ++c) {
         if (h->lists[c].dev) h->retired.push_back(h->lists[c].dev);
         if (h->lists[c].dev_pos) h->retired.push_back(h->lists[c].dev_pos);
-        if (h->lists[c].dev_dord) h->retired.push_back(h->lists[c].dev_dord);
+        if (h->lists[c].dev_kin) h->retired.push_back(h->lists[c].dev_kin);
+        if (h->lists[c].dev_kind) h->retired.push_back(h->lists[c].dev_kind);
         h->lists[c] = fresh[c];
     }
     h->list_tol = tol;
@@ -411,7 +424,6 @@ struct LaunchRec {
     int dig0[2] = {0, 0}, ndig[2] = {0, 0};
     unsigned dig_blocks[2] = {0, 0};
     double eri_flops = 0, dig_flops = 0, quartets = 0, tile_bytes = 0;
-    int kcount[2][8] = {};
 };
 
 struct MolRun {
@@ -441,7 +453,6 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
     for (const MolRun& r : mols) all16 = all16 && dens_stride(r.nd) % 16 == 0;
     for (int c = 0; c < kNumClass; ++c) {
         const int NF = class_nf(c);
-        const int wpb = dig_wpb(NF);
         const Tune tn = tune_of(c);
         const int g16 = all16 && tn.g_max >= 16;
         const int G = g16 ? 16 : 8;
@@ -450,15 +461,29 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
             const int fp32 = mixed && tier == 1;
             LaunchRec L;
             long long used = 0;
+            // digestion tasks per pass and XCD; workgroup 8 k + x of a launch runs
+            // on XCD x and takes task k of that XCD.  A bra pair's pieces and
+            // density groups all go to one XCD, consecutively, so the tasks an
+            // XCD runs together read the same density rows through its L2;
+            // blocks go to the XCD with the least work so far.
+            std::vector<DigItem> xq[2][8];
+            double xwork[8] = {};
             auto flush = [&]() {
                 if (L.neri > 0) {
                     for (int ps = 0; ps < 2; ++ps) {
-                        int kmax = 0;
-                        for (int x = 0; x < 8; ++x) kmax = std::max(kmax, L.kcount[ps][x]);
-                        L.dig_blocks[ps] = static_cast<unsigned>(8 * ((kmax + wpb - 1) / wpb));
+                        size_t kmax = 0;
+                        for (int x = 0; x < 8; ++x) kmax = std::max(kmax, xq[ps][x].size());
+                        DigItem idle{};
+                        for (size_t k = 0; k < kmax; ++k)
+                            for (int x = 0; x < 8; ++x) wp.dig[ps].push_back(k < xq[ps][x].size() ? xq[ps][x][k] : idle);
+                        L.ndig[ps] = static_cast<int>(8 * kmax);
+                        L.dig_blocks[ps] = static_cast<unsigned>(8 * kmax);
                     }
                     wp.launches.push_back(L);
                 }
+                for (auto& v : xq)
+                    for (auto& w : v) w.clear();
+                for (double& w : xwork) w = 0.0;
                 LaunchRec fresh;
                 fresh.cls = c;
                 fresh.fp32 = fp32;
@@ -504,11 +529,14 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     L.neri++;
                     L.eri_blocks += (n + 255) / 256;
                     for (int k = b0; k < b1; ++k) {
+                        const int x = static_cast<int>(std::min_element(xwork, xwork + 8) - xwork);
+                        xwork[x] += static_cast<double>(CL.blocks[k].y) * ngroups;
                         for (int ps = 0; ps < (o->want_k ? 2 : 1); ++ps) {
                             for (int p0 = 0; p0 < CL.blocks[k].y; p0 += piece) {
                                 DigItem d{};
-                                d.quartets = CL.dev;
-                                d.order = ps ? CL.dev_dord : CL.dev_pos;
+                                d.kin = ps ? CL.dev_kind : CL.dev_kin;
+                                d.pos = CL.dev_pos;
+                                d.bra = CL.block_bra[k];
                                 d.blk0 = CL.blocks[k].x;
                                 d.chunk_q0 = q0;
                                 d.chunk_n = n;
@@ -516,12 +544,11 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                                 d.p0 = p0;
                                 d.plen = std::min(piece, CL.blocks[k].y - p0);
                                 d.mol = static_cast<int>(mi);
-                                d.ngroups = ngroups;
-                                const int x = L.ndig[ps] % 8;
-                                d.kstart = L.kcount[ps][x];
-                                L.kcount[ps][x] += ngroups;
-                                wp.dig[ps].push_back(d);
-                                L.ndig[ps]++;
+                                auto& q = xq[ps][x];
+                                for (int g = 0; g < ngroups; ++g) {
+                                    d.grp = g;
+                                    q.push_back(d);
+                                }
                             }
                         }
                     }
@@ -699,6 +726,8 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     }
     h->f0_int[ns] = fc;
     h->nc = fc;
+    if (fc > 0xffff)
+        return fail(JK_EUNSUPPORTED, "jk_create_basis: %d Cartesian functions (at most 65535)", fc);
 
     // shell pairs (a >= b internal, la >= lb) and primitive pairs
     h->pair_id.assign(static_cast<size_t>(ns) * ns, -1);
@@ -851,7 +880,6 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         DigestArgs da[2]{};
         for (int ps = 0; ps < 2; ++ps) {
             da[ps].items = d_dig[ps] + L.dig0[ps];
-            da[ps].nitems = L.ndig[ps];
             da[ps].mol0 = mol0;
             da[ps].mols = d_mols;
             da[ps].tiles = tiles;

@@ -52,13 +52,9 @@ __host__ __device__ inline int quartet_class(int X, int Y) { return X * (X + 1) 
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
-// Digestion geometry of a class with nf Cartesian functions per quartet:
-// quartets staged per chunk (a multiple of the MFMA k-depth 4) and waves per
-// workgroup, so that a workgroup's LDS stays near 52 KB (3 workgroups per CU).
+// Quartets a digestion workgroup stages in LDS per chunk for a class with nf
+// Cartesian functions per quartet (a multiple of the MFMA k-depth 4; at most
+// 26 KB of LDS per chunk).
 __host__ __device__ constexpr int dig_qb(int nf) { return nf <= 90 ? 16 : (nf <= 170 ? 8 : 4); }
-__host__ __device__ constexpr int dig_lds_doubles(int nf) { return nf * (dig_qb(nf) + 1); }
-__host__ __device__ constexpr int dig_wpb(int nf) {
-    return dig_lds_doubles(nf) * 8 <= 16384 ? 4 : (dig_lds_doubles(nf) * 8 <= 32768 ? 2 : 1);
-}
 
 }  // namespace jk

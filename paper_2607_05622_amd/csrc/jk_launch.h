@@ -61,32 +61,33 @@ struct EriTileArgs {
     void* scratch;          // (e0|cd) of pass-evaluated classes, same offsets as tiles
 };
 
-// One digestion unit: a piece of the quartets of one bra pair (a "block":
-// the bra pair's quartets of one class and tier, consecutive in the class
-// list with ket pairs in (c, d) order), digested by ngroups waves of 8 or
-// 16 densities each.  Pass C walks the block in list order (runs of equal
-// ket shell c), pass D in the order sorted by (d, c) (runs of equal d).
+// One digestion task, the work of one workgroup: a piece of the quartets of
+// one bra pair (a "block": the bra pair's quartets of one class and tier,
+// consecutive in the class list with ket pairs in (c, d) order) and one
+// group of 8 or 16 densities.  Pass C walks the block in list order (runs
+// of equal ket shell c), pass D in the order sorted by (d, c) (runs of equal
+// d).  A launch holds one task per workgroup; plen = 0 marks an idle one.
 struct DigItem {
-    const int2* quartets;   // the molecule's class list
-    const int* order;       // pass C: D-order position of each list quartet within its block;
-                            // pass D: block offset of the quartet at each D-order position
+    const int2* kin;        // per position of this pass's order: ket shells (c | d << 16) and
+                            // their first Cartesian functions (fc | fd << 16)
+    const int* pos;         // pass C: (d, c)-order position of each list quartet within its block
     long long blk0;         // class-list index of the block's first quartet
     long long chunk_q0;     // class-list index of the first quartet of the block's tile item
     long long chunk_n;      // tile stride of that item
     long long tile_off;     // element offset of that item's tiles (and of its D-order copy)
     int p0, plen;           // the piece: positions [p0, p0 + plen) in this pass's order
-    int mol, ngroups, kstart, pad;   // kstart: first wave task of the item on its XCD
+    int mol, grp;           // molecule, density group
+    int bra, pad;           // the bra shell pair
 };
 
 struct DigestArgs {
-    const DigItem* items;
-    int nitems;
+    const DigItem* items;   // one per workgroup
     MolDesc mol0;
     const MolDesc* mols;
     const void* tiles;      // [NF][n] per tile item, double or float
     void* dcopy;            // D-order copy [n][NF] per tile item, written by pass C
     int want_j, want_k;
-    unsigned nblocks;       // 8 x the largest per-XCD workgroup count
+    unsigned nblocks;       // workgroups (tasks) of the launch
 };
 
 // one launcher pair per canonical class index, defined in jk_class.hip
