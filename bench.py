@@ -77,7 +77,11 @@ def serve_bench(args):
     bases = [m.basis for m in mols]
     stream = synth.request_stream(args.requests, 1.0)
     reqs_d = [synth.request_densities(mols[r["mol"]].meta["orbitals"], r["nd"], r["seed"]) for r in stream]
-    handles = [jk.JKBasis(bb) for bb in bases]
+    log(f"serve: {len(stream)} requests, {sum(r['nd'] for r in stream)} densities")
+    handles = []
+    for i, bb in enumerate(bases):
+        handles.append(jk.JKBasis(bb))
+        log(f"serve: molecule {i} resident ({bb.nbf()} AO)")
     # capacity of the plain form: mean service time of one request
     o64 = jk.jk_default_opts()
     Dt = [torch.tensor(d, device=dev) for d in reqs_d]
@@ -87,6 +91,9 @@ def serve_bench(args):
     t0 = time.perf_counter()
     for i, r in enumerate(stream):
         jk.jk_build(handles[r["mol"]].h, Dt[i], opts=o64)
+        if i % 20 == 19:
+            torch.cuda.synchronize()
+            log(f"serve: capacity run {i + 1}/{len(stream)}")
     torch.cuda.synchronize()
     service = (time.perf_counter() - t0) / len(stream)
     rate = args.rate / service
@@ -97,13 +104,16 @@ def serve_bench(args):
     def make():
         return [serve.Request(i, float(arrivals[i]), r["mol"], Dt[i]) for i, r in enumerate(stream)]
 
-    base = serve.one_at_a_time(handles, make(), o64)
+    base = serve.one_at_a_time(handles, make(), o64,
+                                on_progress=lambda d, n: (d % 10 == 0) and log(f"serve: plain {d}/{n} done"))
     log(f"serve: plain FP64 {base['builds_per_s']:.1f} builds/s p50 {base['p50_ms']:.1f} ms")
     for h in handles:
         h.close()
     srv = serve.JKServer(bases, n_slots=4, precision=jk.JK_MIXED, max_batch=16)
-    srv.warm_graphs(max_nd=64)
-    res = srv.run(make(), on_progress=lambda d, n: (d % 20 == 0) and log(f"serve: {d}/{n} done"))
+    srv.warm_graphs(max_nd=64, on_progress=lambda s, m: log(f"serve: graphs of slot {s} molecule {m} captured"))
+    res = srv.run(make(), on_progress=lambda d, n: log(f"serve: mixed server {d}/{n} done"),
+                  on_launch=lambda si, b: log(f"serve: slot {si} launches {len(b)} request(s): " +
+                                              " ".join(f"{bases[r.mol].nbf()}AOx{r.nd}" for r in b)))
     srv.close()
     log(f"serve: mixed server {res['builds_per_s']:.1f} builds/s p50 {res['p50_ms']:.1f} ms")
     print(json.dumps({"metric": METRIC, "value": res["builds_per_s"], "unit": "builds/s", "n_gpus": 1,
@@ -128,7 +138,7 @@ def main():
                     help="serve a Poisson request stream over 16 resident molecules instead")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--rate", type=float, default=1.0, help="arrival rate / FP64 one-at-a-time capacity")
-    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -56,6 +56,28 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// The task of the calling workgroup: its block item, piece and density
+// group.  Workgroup b runs on XCD b % 8 and takes task b / 8 of that XCD,
+// found by bisection over the XCD's items.  Returns nullptr when idle.
+__device__ __forceinline__ const DigItem* dig_task(const DigestArgs& a, int& p0, int& plen, int& grp) {
+    const int b = blockIdx.x, xcd = b & 7, task = b >> 3;
+    int lo = 0, hi = a.nitems / 8 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.items[xcd + 8 * mid].kstart <= task) lo = mid;
+        else hi = mid - 1;
+    }
+    const DigItem* it = a.items + xcd + 8 * lo;
+    if (it->kstart > task) return nullptr;
+    const int local = task - it->kstart;
+    const int pc = local / it->ngroups;
+    grp = local - pc * it->ngroups;
+    p0 = pc * it->piece;
+    if (p0 >= it->len) return nullptr;
+    plen = min(it->piece, it->len - p0);
+    return it;
+}
+
 template <int LA, int LB, int LC, int LD>
 struct DigShape {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
@@ -148,9 +170,10 @@ __global__ __launch_bounds__(192) void k_digest_c(DigestArgs a) {
     __shared__ int sV[QB];
     __shared__ int sP[QB];
 
-    const DigItem it = a.items[blockIdx.x];
-    if (it.plen == 0) return;
-    const int grp = it.grp;
+    int p0 = 0, plen = 0, grp = 0;
+    const DigItem* itp = dig_task(a, p0, plen, grp);
+    if (!itp) return;
+    const DigItem it = *itp;
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
@@ -196,8 +219,8 @@ __global__ __launch_bounds__(192) void k_digest_c(DigestArgs a) {
 #pragma unroll
     for (int t = 0; t < NACC; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    const int pend = it.p0 + it.plen;
-    for (int p = it.p0; p < pend;) {
+    const int pend = p0 + plen;
+    for (int p = p0; p < pend;) {
         int2 kv;
         bool more;
         const int n = dig_chunk<QB>(kin, p, pend, lane, 0, kv, more);
@@ -347,9 +370,10 @@ __global__ __launch_bounds__(128) void k_digest_d(DigestArgs a) {
     __shared__ double sT[NF * QBP];
     __shared__ int sV[QB];
 
-    const DigItem it = a.items[blockIdx.x];
-    if (it.plen == 0) return;
-    const int grp = it.grp;
+    int p0 = 0, plen = 0, grp = 0;
+    const DigItem* itp = dig_task(a, p0, plen, grp);
+    if (!itp) return;
+    const DigItem it = *itp;
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
@@ -376,8 +400,8 @@ __global__ __launch_bounds__(128) void k_digest_d(DigestArgs a) {
 #pragma unroll
     for (int t = 0; t < NACC; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    const int pend = it.p0 + it.plen;
-    for (int p = it.p0; p < pend;) {
+    const int pend = p0 + plen;
+    for (int p = p0; p < pend;) {
         int2 kv;
         bool more;
         const int n = dig_chunk<QB>(kin, p, pend, lane, 16, kv, more);

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -461,28 +462,37 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
             const int fp32 = mixed && tier == 1;
             LaunchRec L;
             long long used = 0;
-            // digestion tasks per pass and XCD; workgroup 8 k + x of a launch runs
-            // on XCD x and takes task k of that XCD.  A bra pair's pieces and
-            // density groups all go to one XCD, consecutively, so the tasks an
-            // XCD runs together read the same density rows through its L2;
-            // blocks go to the XCD with the least work so far.
+            // digestion items (blocks) per pass and XCD; workgroup 8 k + x of a
+            // launch runs on XCD x and takes task k of that XCD.  A bra pair's
+            // pieces and density groups all run on one XCD, consecutively, so
+            // the tasks an XCD runs together read the same density rows
+            // through its L2; blocks go to the XCD with the least work so far.
             std::vector<DigItem> xq[2][8];
+            int xtasks[2][8] = {};
             double xwork[8] = {};
             auto flush = [&]() {
                 if (L.neri > 0) {
                     for (int ps = 0; ps < 2; ++ps) {
                         size_t kmax = 0;
-                        for (int x = 0; x < 8; ++x) kmax = std::max(kmax, xq[ps][x].size());
+                        int tmax = 0;
+                        for (int x = 0; x < 8; ++x) {
+                            kmax = std::max(kmax, xq[ps][x].size());
+                            tmax = std::max(tmax, xtasks[ps][x]);
+                        }
                         DigItem idle{};
+                        idle.kstart = std::numeric_limits<int>::max();
+                        idle.ngroups = 1;
                         for (size_t k = 0; k < kmax; ++k)
                             for (int x = 0; x < 8; ++x) wp.dig[ps].push_back(k < xq[ps][x].size() ? xq[ps][x][k] : idle);
                         L.ndig[ps] = static_cast<int>(8 * kmax);
-                        L.dig_blocks[ps] = static_cast<unsigned>(8 * kmax);
+                        L.dig_blocks[ps] = static_cast<unsigned>(8 * tmax);
                     }
                     wp.launches.push_back(L);
                 }
                 for (auto& v : xq)
                     for (auto& w : v) w.clear();
+                for (auto& v : xtasks)
+                    for (int& t : v) t = 0;
                 for (double& w : xwork) w = 0.0;
                 LaunchRec fresh;
                 fresh.cls = c;
@@ -532,24 +542,21 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                         const int x = static_cast<int>(std::min_element(xwork, xwork + 8) - xwork);
                         xwork[x] += static_cast<double>(CL.blocks[k].y) * ngroups;
                         for (int ps = 0; ps < (o->want_k ? 2 : 1); ++ps) {
-                            for (int p0 = 0; p0 < CL.blocks[k].y; p0 += piece) {
-                                DigItem d{};
-                                d.kin = ps ? CL.dev_kind : CL.dev_kin;
-                                d.pos = CL.dev_pos;
-                                d.bra = CL.block_bra[k];
-                                d.blk0 = CL.blocks[k].x;
-                                d.chunk_q0 = q0;
-                                d.chunk_n = n;
-                                d.tile_off = used;
-                                d.p0 = p0;
-                                d.plen = std::min(piece, CL.blocks[k].y - p0);
-                                d.mol = static_cast<int>(mi);
-                                auto& q = xq[ps][x];
-                                for (int g = 0; g < ngroups; ++g) {
-                                    d.grp = g;
-                                    q.push_back(d);
-                                }
-                            }
+                            DigItem d{};
+                            d.kin = ps ? CL.dev_kind : CL.dev_kin;
+                            d.pos = CL.dev_pos;
+                            d.bra = CL.block_bra[k];
+                            d.blk0 = CL.blocks[k].x;
+                            d.chunk_q0 = q0;
+                            d.chunk_n = n;
+                            d.tile_off = used;
+                            d.len = CL.blocks[k].y;
+                            d.piece = piece;
+                            d.ngroups = ngroups;
+                            d.kstart = xtasks[ps][x];
+                            d.mol = static_cast<int>(mi);
+                            xtasks[ps][x] += (d.len + piece - 1) / piece * ngroups;
+                            xq[ps][x].push_back(d);
                         }
                     }
                     const double ef = n * (prim_avg * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
@@ -880,6 +887,7 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         DigestArgs da[2]{};
         for (int ps = 0; ps < 2; ++ps) {
             da[ps].items = d_dig[ps] + L.dig0[ps];
+            da[ps].nitems = L.ndig[ps];
             da[ps].mol0 = mol0;
             da[ps].mols = d_mols;
             da[ps].tiles = tiles;

@@ -61,12 +61,15 @@ struct EriTileArgs {
     void* scratch;          // (e0|cd) of pass-evaluated classes, same offsets as tiles
 };
 
-// One digestion task, the work of one workgroup: a piece of the quartets of
-// one bra pair (a "block": the bra pair's quartets of one class and tier,
-// consecutive in the class list with ket pairs in (c, d) order) and one
-// group of 8 or 16 densities.  Pass C walks the block in list order (runs
-// of equal ket shell c), pass D in the order sorted by (d, c) (runs of equal
-// d).  A launch holds one task per workgroup; plen = 0 marks an idle one.
+// Digestion work of one bra pair (a "block": the bra pair's quartets of one
+// class and tier, consecutive in the class list with ket pairs in (c, d)
+// order).  Its tasks, one workgroup each, are the pieces of at most `piece`
+// positions times the density groups of 8 or 16: task kstart + pc * ngroups
+// + g digests piece pc for group g.  Pass C walks the block in list order
+// (runs of equal ket shell c), pass D in the order sorted by (d, c) (runs of
+// equal d).  Blocks are dealt to the XCDs: item i of a launch belongs to XCD
+// i % 8, whose tasks are numbered from 0 in item order (idle padding items
+// have kstart = INT_MAX).
 struct DigItem {
     const int2* kin;        // per position of this pass's order: ket shells (c | d << 16) and
                             // their first Cartesian functions (fc | fd << 16)
@@ -75,19 +78,20 @@ struct DigItem {
     long long chunk_q0;     // class-list index of the first quartet of the block's tile item
     long long chunk_n;      // tile stride of that item
     long long tile_off;     // element offset of that item's tiles (and of its D-order copy)
-    int p0, plen;           // the piece: positions [p0, p0 + plen) in this pass's order
-    int mol, grp;           // molecule, density group
-    int bra, pad;           // the bra shell pair
+    int len, piece;         // quartets of the block, positions per piece
+    int ngroups, kstart;    // density groups; first task on its XCD
+    int mol, bra;           // molecule, bra shell pair
 };
 
 struct DigestArgs {
-    const DigItem* items;   // one per workgroup
+    const DigItem* items;
+    int nitems;             // a multiple of 8
     MolDesc mol0;
     const MolDesc* mols;
     const void* tiles;      // [NF][n] per tile item, double or float
     void* dcopy;            // D-order copy [n][NF] per tile item, written by pass C
     int want_j, want_k;
-    unsigned nblocks;       // workgroups (tasks) of the launch
+    unsigned nblocks;       // 8 x the largest per-XCD task count
 };
 
 // one launcher pair per canonical class index, defined in jk_class.hip

@@ -122,16 +122,18 @@ class JKServer:
         slot.graphs[key] = (g, D, J, K)
         return slot.graphs[key]
 
-    def warm_graphs(self, mols=None, max_nd=None):
+    def warm_graphs(self, mols=None, max_nd=None, on_progress=None):
         """Capture the graphs of every (slot, molecule, power-of-two nd)."""
         mols = range(len(self.handles)) if mols is None else mols
         max_nd = max_nd or self.graph_max_nd
-        for slot in self.slots:
+        for si, slot in enumerate(self.slots):
             for m in mols:
                 ndb = 1
                 while ndb <= max_nd:
                     self._graph(slot, m, ndb)
                     ndb *= 2
+                if on_progress:
+                    on_progress(si, m)
         torch.cuda.synchronize(self.dev)
 
     # ------------------------------------------------------------ launch --
@@ -172,9 +174,11 @@ class JKServer:
         slot.busy = list(reqs)
 
     # --------------------------------------------------------------- run --
-    def run(self, requests, on_progress=None):
+    def run(self, requests, on_progress=None, on_launch=None):
         """Serve `requests` (sorted by arrival).  Returns summary statistics;
-        each request gets J, K, done_ms and its slot."""
+        each request gets J, K, done_ms and its slot.  on_launch(slot, reqs)
+        is called for every launch, on_progress(done, total) on every
+        completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             if not self.fits_alone(r):
@@ -214,6 +218,8 @@ class JKServer:
                     for r in batch:
                         queue.remove(r)
                         r.slot = si
+                    if on_launch:
+                        on_launch(si, batch)
                     self._launch(slot, batch)
                     progressed = True
             if not progressed:
@@ -241,7 +247,7 @@ def summarize(reqs):
                 graph_fraction=float(np.mean([r.graph for r in reqs])))
 
 
-def one_at_a_time(handles, reqs, opts, device="cuda:0"):
+def one_at_a_time(handles, reqs, opts, device="cuda:0", on_progress=None):
     """The plain form: one request after the other on one stream, each a
     separate jk_build as soon as it has arrived and the previous one is done."""
     dev = torch.device(device)
@@ -263,4 +269,6 @@ def one_at_a_time(handles, reqs, opts, device="cuda:0"):
         ev.synchronize()
         r.done_ms = start.elapsed_time(ev)
         r.batch = 1
+        if on_progress:
+            on_progress(r.index + 1, len(reqs))
     return summarize(reqs)
