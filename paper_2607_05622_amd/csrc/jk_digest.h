@@ -56,7 +56,7 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// The task of the calling workgroup: its block item, piece and density
+// The task of the calling workgroup: its block item, part and density
 // group.  Workgroup b runs on XCD b % 8 and takes task b / 8 of that XCD,
 // found by bisection over the XCD's items.  Returns nullptr when idle.
 __device__ __forceinline__ const DigItem* dig_task(const DigestArgs& a, int& p0, int& plen, int& grp) {
@@ -71,10 +71,11 @@ __device__ __forceinline__ const DigItem* dig_task(const DigestArgs& a, int& p0,
     if (it->kstart > task) return nullptr;
     const int local = task - it->kstart;
     const int pc = local / it->ngroups;
+    if (pc >= it->nparts) return nullptr;
     grp = local - pc * it->ngroups;
-    p0 = pc * it->piece;
-    if (p0 >= it->len) return nullptr;
-    plen = min(it->piece, it->len - p0);
+    const gptr<const int> parts = glob(it->parts);
+    p0 = parts[pc];
+    plen = (pc + 1 < it->nparts ? parts[pc + 1] : it->len) - p0;
     return it;
 }
 

@@ -97,11 +97,12 @@ const double kSphD[5][6] = {
 int class_nf(int cls) { return kClassCost[cls].nfunc; }
 
 // Schedule tunables per class (process-wide; chosen by jk_autotune): the
-// length cap of a digestion piece (quartets of one bra pair digested by one
-// wave) and the densities a digestion wave takes at once (16, or 8 when
-// g_max < 16 or the batch has at most 8 densities).
+// length cap of a digestion part (a run of one bra pair's quartets with one
+// ket shell, digested by one workgroup; longer runs are cut) and the
+// densities a digestion workgroup takes at once (16, or 8 when g_max < 16 or
+// the batch has at most 8 densities).
 struct Tune {
-    int seg_max = 32;
+    int seg_max = 128;
     int g_max = 16;
 };
 std::mutex g_tune_mu;
@@ -125,6 +126,11 @@ struct ClassList {
     int2* dev = nullptr;
     std::vector<int2> blocks;        // (first quartet, count)
     std::vector<int> block_bra;      // bra shell pair of each block
+    // digestion parts per pass (0: runs of equal c in list order, 1: runs of
+    // equal d in (d, c) order, cut at the tunable cap): block k's parts start
+    // at positions parts[ps][part_off[ps][k] ..] of the block
+    std::vector<int> part_off[2];
+    int* dev_parts[2] = {nullptr, nullptr};
     int* dev_pos = nullptr;          // per quartet: its position in the block's (d, c) order
     int2* dev_kin = nullptr;         // per quartet, list order: (c | d << 16, fc | fd << 16) of the ket
     int2* dev_kind = nullptr;        // the same per position of the blocks' (d, c) orders
@@ -169,6 +175,7 @@ struct jk_basis_s {
     ClassList lists[kNumClass];
     std::vector<void*> retired;
     int list_gen = 0;                  // bumped whenever the lists are rebuilt
+    int tune_gen = -1;                 // tunables the lists' digestion parts were cut with
     std::vector<CachedPlan*> plans;    // single-molecule plans (freed by jk_destroy)
     double stats[6] = {0, 0, 0, 0, 0, 0};
     // measurement: event pairs around integral / digestion launches
@@ -198,6 +205,8 @@ struct jk_basis_s {
             (void)hipFree(l.dev_pos);
             (void)hipFree(l.dev_kin);
             (void)hipFree(l.dev_kind);
+            (void)hipFree(l.dev_parts[0]);
+            (void)hipFree(l.dev_parts[1]);
         }
         for (auto* p : retired) (void)hipFree(p);
         for (auto& r : prof) {
@@ -346,8 +355,9 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             F.prim_quartets[1] = primq[1];
             // blocks (one bra pair, one tier), their (d, c) orders and the
             // ket shells and functions the digestion reads per position
-            std::vector<int> pos(out.size()), idx;
+            std::vector<int> pos(out.size()), idx, parts[2];
             std::vector<int2> kin(out.size()), kind(out.size());
+            const int cap = std::max(4, tune_of(cls).seg_max);
             for (size_t q = 0; q < out.size(); ++q) {
                 const PairInfo& Q = h->pairs[out[q].y];
                 kin[q] = make_int2(Q.sa | (Q.sb << 16), Q.fa | (Q.fb << 16));
@@ -370,21 +380,38 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                         kind[q + p] = kin[q + idx[p]];
                         pos[q + idx[p]] = static_cast<int>(p);
                     }
+                    // parts: runs of equal c (pass C) and of equal d (pass D)
+                    for (int ps = 0; ps < 2; ++ps) {
+                        const std::vector<int2>& kv = ps ? kind : kin;
+                        const int shift = ps ? 16 : 0;
+                        F.part_off[ps].push_back(static_cast<int>(parts[ps].size()));
+                        for (size_t p = q; p < e;) {
+                            size_t r = p + 1;
+                            while (r < e && ((kv[r].x >> shift) & 0xffff) == ((kv[p].x >> shift) & 0xffff)) ++r;
+                            for (size_t c = p; c < r; c += cap) parts[ps].push_back(static_cast<int>(c - q));
+                            p = r;
+                        }
+                    }
                     q = e;
                 }
                 if (t == 0) F.nblk64 = static_cast<int>(F.blocks.size());
             }
+            for (int ps = 0; ps < 2; ++ps) F.part_off[ps].push_back(static_cast<int>(parts[ps].size()));
             if (!out.empty()) {
                 int rc = upload(&F.dev, out);
                 if (!rc) rc = upload(&F.dev_pos, pos);
                 if (!rc) rc = upload(&F.dev_kin, kin);
                 if (!rc) rc = upload(&F.dev_kind, kind);
+                if (!rc) rc = upload(&F.dev_parts[0], parts[0]);
+                if (!rc) rc = upload(&F.dev_parts[1], parts[1]);
                 if (rc) {
                     for (auto& f : fresh) {
                         (void)hipFree(f.dev);
                         (void)hipFree(f.dev_pos);
                         (void)hipFree(f.dev_kin);
                         (void)hipFree(f.dev_kind);
+                        (void)hipFree(f.dev_parts[0]);
+                        (void)hipFree(f.dev_parts[1]);
                     }
                     return rc;
                 }
@@ -396,11 +423,17 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
         if (h->lists[c].dev_pos) h->retired.push_back(h->lists[c].dev_pos);
         if (h->lists[c].dev_kin) h->retired.push_back(h->lists[c].dev_kin);
         if (h->lists[c].dev_kind) h->retired.push_back(h->lists[c].dev_kind);
+        for (int ps = 0; ps < 2; ++ps)
+            if (h->lists[c].dev_parts[ps]) h->retired.push_back(h->lists[c].dev_parts[ps]);
         h->lists[c] = fresh[c];
     }
     h->list_tol = tol;
     h->list_bound = bound;
     h->list_gen++;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        h->tune_gen = g_tune_gen;
+    }
     return JK_OK;
 }
 
@@ -410,7 +443,12 @@ int ensure_lists(jk_basis_s* h, double tol, double bound) {
     std::lock_guard<std::mutex> g(h->mu);
     const bool tol_ok = h->list_tol >= 0 && h->list_tol <= tol;
     const bool bound_ok = bound < 0 || h->list_bound == bound;
-    if (tol_ok && bound_ok) return JK_OK;
+    int tg;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tg = g_tune_gen;
+    }
+    if (tol_ok && bound_ok && h->tune_gen == tg) return JK_OK;
     return build_lists(h, tol_ok ? h->list_tol : tol, bound < 0 ? h->list_bound : bound);
 }
 
@@ -457,7 +495,6 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
         const Tune tn = tune_of(c);
         const int g16 = all16 && tn.g_max >= 16;
         const int G = g16 ? 16 : 8;
-        const int piece = std::max(1, tn.seg_max);
         for (int tier = 0; tier < (mixed ? 2 : 1); ++tier) {
             const int fp32 = mixed && tier == 1;
             LaunchRec L;
@@ -551,11 +588,12 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                             d.chunk_n = n;
                             d.tile_off = used;
                             d.len = CL.blocks[k].y;
-                            d.piece = piece;
+                            d.parts = CL.dev_parts[ps] + CL.part_off[ps][k];
+                            d.nparts = CL.part_off[ps][k + 1] - CL.part_off[ps][k];
                             d.ngroups = ngroups;
                             d.kstart = xtasks[ps][x];
                             d.mol = static_cast<int>(mi);
-                            xtasks[ps][x] += (d.len + piece - 1) / piece * ngroups;
+                            xtasks[ps][x] += d.nparts * ngroups;
                             xq[ps][x].push_back(d);
                         }
                     }
@@ -1291,7 +1329,7 @@ int jk_tune_load(const char* path) {
 int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o,
                 const char* cache_path) {
     if (!h || !o || nd < 1 || !D || !J || !K) return fail(JK_EINVAL, "jk_autotune: bad arguments");
-    static const int kSeg[] = {64, 128, 256, 512, 1024};
+    static const int kSeg[] = {16, 32, 64, 128, 256};
     static const int kG[] = {8, 16};
     double best_ms[kNumClass];
     Tune best[kNumClass];

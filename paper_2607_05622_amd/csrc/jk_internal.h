@@ -53,8 +53,10 @@ __host__ __device__ inline int quartet_class(int X, int Y) { return X * (X + 1) 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
 // Quartets a digestion workgroup stages in LDS per chunk for a class with nf
-// Cartesian functions per quartet (a multiple of the MFMA k-depth 4; at most
-// 26 KB of LDS per chunk).
-__host__ __device__ constexpr int dig_qb(int nf) { return nf <= 90 ? 16 : (nf <= 170 ? 8 : 4); }
+// Cartesian functions per quartet (a multiple of the MFMA k-depth 4; about
+// 24 KB of LDS per chunk, 52 KB for (dd|dd)).
+__host__ __device__ constexpr int dig_qb(int nf) {
+    return nf <= 90 ? 32 : (nf <= 170 ? 16 : (nf <= 324 ? 8 : 4));
+}
 
 }  // namespace jk

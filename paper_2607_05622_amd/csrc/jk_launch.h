@@ -63,11 +63,11 @@ struct EriTileArgs {
 
 // Digestion work of one bra pair (a "block": the bra pair's quartets of one
 // class and tier, consecutive in the class list with ket pairs in (c, d)
-// order).  Its tasks, one workgroup each, are the pieces of at most `piece`
-// positions times the density groups of 8 or 16: task kstart + pc * ngroups
-// + g digests piece pc for group g.  Pass C walks the block in list order
-// (runs of equal ket shell c), pass D in the order sorted by (d, c) (runs of
-// equal d).  Blocks are dealt to the XCDs: item i of a launch belongs to XCD
+// order).  Its tasks, one workgroup each, are its parts times the density
+// groups of 8 or 16: task kstart + pc * ngroups + g digests part pc for
+// group g.  Pass C walks the block in list order and its parts are the runs
+// of equal ket shell c; pass D walks the order sorted by (d, c) and its parts
+// are the runs of equal d (runs longer than a cap are cut).  Blocks are dealt to the XCDs: item i of a launch belongs to XCD
 // i % 8, whose tasks are numbered from 0 in item order (idle padding items
 // have kstart = INT_MAX).
 struct DigItem {
@@ -78,7 +78,8 @@ struct DigItem {
     long long chunk_q0;     // class-list index of the first quartet of the block's tile item
     long long chunk_n;      // tile stride of that item
     long long tile_off;     // element offset of that item's tiles (and of its D-order copy)
-    int len, piece;         // quartets of the block, positions per piece
+    const int* parts;       // start position of each part within the block
+    int len, nparts;        // quartets and parts of the block
     int ngroups, kstart;    // density groups; first task on its XCD
     int mol, bra;           // molecule, bra shell pair
 };

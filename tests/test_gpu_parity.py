@@ -248,6 +248,35 @@ def test_mixed_medium_workload(dev):
         assert np.all(np.abs(Km[sl] - Kb) <= 1e-8 * scale_k)
 
 
+def test_large_workload_fp64_and_mixed(dev):
+    """620 AO, 40 non-symmetric densities (the memory-ceiling molecule):
+    FP64 against the oracle on sampled shell-pair blocks of every pair
+    class, mixed against FP64 per density over whole matrices and against
+    the oracle on the same blocks."""
+    w = synth.config2()
+    print(f"large workload: {w.basis.nbf()} AO, {w.D.shape[0]} densities", flush=True)
+    J64, K64 = gpu_jk(w.basis, w.D, dev)
+    Jm, Km = gpu_jk(w.basis, w.D, dev, precision=jk.JK_MIXED)
+    l = w.basis.shell_l
+    rng = np.random.default_rng(2)
+    pairs = []
+    for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]:
+        A = [int(s) for s in np.nonzero(l == la)[0]]
+        B = [int(s) for s in np.nonzero(l == lb)[0]]
+        pairs.append((A[int(rng.integers(len(A)))], B[int(rng.integers(len(B)))]))
+    fo = w.basis.func_offsets()
+    scale_j = np.max(np.abs(J64), axis=(1, 2))[:, None, None]
+    scale_k = np.max(np.abs(K64), axis=(1, 2))[:, None, None]
+    for (a, c), (Jb, Kb) in zip(pairs, oracle.jk_blocks(w.basis, w.D, pairs, 1e-12)):
+        sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
+        assert maxabs(J64[sl], Jb) <= TOL and maxabs(K64[sl], Kb) <= TOL, (a, c)
+        assert np.all(np.abs(Jm[sl] - Jb) <= 1e-8 * scale_j) and np.all(np.abs(Km[sl] - Kb) <= 1e-8 * scale_k)
+    ej, ek = rel_frob(Jm, J64), rel_frob(Km, K64)
+    print("large mixed vs fp64 per density: max rel-Frobenius J %.2e K %.2e" % (ej.max(), ek.max()))
+    assert np.all(ej <= 1e-8) and np.all(ek <= 1e-8)
+    assert maxabs(J64, J64.transpose(0, 2, 1)) <= 1e-12 * np.max(np.abs(J64))
+
+
 # ------------------------------------------------------- batched launch ----
 
 def _batch(bases, Ds, dev, **opts):
