@@ -349,9 +349,12 @@ def emit_all(path, counts_path=None):
         L = info["L"]
         src.append("template <typename R> struct Eri%s {" % tag)
         src.append("  static constexpr int L = %d, NACC = %d, NF = %d;" % (L, info["nacc"], info["nfunc"]))
+        src.append("  template <typename T> using With = Eri%s<T>;   // the same class in precision T" % tag)
         src.append("  static constexpr int LA = %d, LB = %d, LC = %d, LD = %d;" % c)
         # VRR: needs F[0..L], PA, WP, QC, WQ, o2p_k, o2q_k, o2pq_k, rp, rq
-        src.append("  __device__ static __forceinline__ void vrr(const R* __restrict__ F, const VrrCoef<R>& k, R* __restrict__ acc) {")
+        src.append("  // vertical recurrence in precision R, contracted into accumulators of type A")
+        src.append("  template <typename A>")
+        src.append("  __device__ static __forceinline__ void vrr(const R* __restrict__ F, const VrrCoef<R>& k, A* __restrict__ acc) {")
         src.append("    const R PAx = k.PA[0], PAy = k.PA[1], PAz = k.PA[2];")
         src.append("    const R WPx = k.WP[0], WPy = k.WP[1], WPz = k.WP[2];")
         src.append("    const R QCx = k.QC[0], QCy = k.QC[1], QCz = k.QC[2];")
@@ -379,7 +382,7 @@ def emit_all(path, counts_path=None):
             gn = [g["n"] for g in sp["groups"]]
             src.append("  static constexpr int NE = %d, NCD = %d, NAB = %d, NG = %d, GMAX = %d;" % (
                 sp["NE"], sp["NCD"], sp["NAB"], len(gn), max(gn)))
-            src.append("  template <int G> __device__ static __forceinline__ void vrr_group(const R* __restrict__ F, const VrrCoef<R>& k, R* __restrict__ acc) {")
+            src.append("  template <int G, typename A> __device__ static __forceinline__ void vrr_group(const R* __restrict__ F, const VrrCoef<R>& k, A* __restrict__ acc) {")
             src.append("    const R PAx = k.PA[0], PAy = k.PA[1], PAz = k.PA[2];")
             src.append("    const R WPx = k.WP[0], WPy = k.WP[1], WPz = k.WP[2];")
             src.append("    const R QCx = k.QC[0], QCy = k.QC[1], QCz = k.QC[2];")

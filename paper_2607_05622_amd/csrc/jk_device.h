@@ -14,6 +14,17 @@ namespace jk {
 
 #include "eri_gen.inc"
 
+// Pointers into device memory reached through descriptors are generic to
+// the compiler; naming them global makes their accesses global (not flat)
+// instructions, whose completion is counted apart from LDS and scalar
+// traffic, so loads stay in flight across other work.
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T* p) {
+    return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------- Boys ---
 
 // F_m(T), m = 0..L, multiplied by pref.  T < kBoysTMax: seven-term Taylor
@@ -23,15 +34,14 @@ namespace jk {
 // form F_0 = sqrt(pi/T)/2, F_{m+1} = F_m (2m+1)/(2T); the dropped e^{-T}
 // terms are below 2e-22.
 template <int L>
-__device__ __forceinline__ void boys_f64(double T, double pref, const double* __restrict__ tab,
-                                         double* __restrict__ F) {
+__device__ __forceinline__ void boys_f64(double T, double pref, gptr<const double> tab, double* __restrict__ F) {
     constexpr double inv_odd[16] = {1.0,       1.0 / 3,  1.0 / 5,  1.0 / 7,  1.0 / 9,  1.0 / 11,
                                     1.0 / 13,  1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21, 1.0 / 23,
                                     1.0 / 25,  1.0 / 27, 1.0 / 29, 1.0 / 31};
     if (T < kBoysTMax) {
         const int i = static_cast<int>(T * kBoysInvStep + 0.5);
         const double x = static_cast<double>(i) * (1.0 / kBoysInvStep) - T;   // -(T - T0)
-        const double* __restrict__ r = tab + i * kBoysCols;
+        const gptr<const double> r = tab + i * kBoysCols;
         double f = r[L + 6];
         f = fma(f, x * (1.0 / 6), r[L + 5]);
         f = fma(f, x * (1.0 / 5), r[L + 4]);
@@ -74,12 +84,11 @@ __device__ __forceinline__ void boys_f64(double T, double pref, const double* __
 // recursion), the FP64 asymptotic form beyond it; the FP64 prefactor is
 // applied in FP64 before rounding to FP32.
 template <int L>
-__device__ __forceinline__ void boys_f32(double T, double pref, const float* __restrict__ tab,
-                                         float* __restrict__ F) {
+__device__ __forceinline__ void boys_f32(double T, double pref, gptr<const float> tab, float* __restrict__ F) {
     if (T < kBoysTMax) {
         const int i = static_cast<int>(T * kBoysInvStep + 0.5);
         const float x = static_cast<float>(static_cast<double>(i) * (1.0 / kBoysInvStep) - T);
-        const float* __restrict__ r = tab + i * kBoysCols;
+        const gptr<const float> r = tab + i * kBoysCols;
         float f = r[L + 4];
         f = fmaf(f, x * 0.25f, r[L + 3]);
         f = fmaf(f, x * (1.0f / 3), r[L + 2]);
@@ -119,8 +128,8 @@ __device__ __forceinline__ void boys_f32(double T, double pref, const float* __r
 // Boys values of the working precision R.
 template <int L, typename R>
 __device__ __forceinline__ void boys_r(double T, double pref, const EriTileArgs& a, R* F) {
-    if constexpr (sizeof(R) == 8) boys_f64<L>(T, pref, a.boys, F);
-    else boys_f32<L>(T, pref, a.boys32, F);
+    if constexpr (sizeof(R) == 8) boys_f64<L>(T, pref, glob(a.boys), F);
+    else boys_f32<L>(T, pref, glob(a.boys32), F);
 }
 
 template <typename R>
@@ -170,11 +179,12 @@ __device__ __forceinline__ void prim_setup(const PrimPair& P, const PrimPair& Q,
 
 // Identical decision in every kernel: keep (ab|cd) iff Q_ab Q_cd >= tol and
 // Q_ab Q_cd * max(Dmax over ab, cd, ac, ad, bc, bd) >= tol.
-__device__ __forceinline__ bool keep_quartet(const PairInfo& P, const PairInfo& Q,
-                                             const double* __restrict__ dmax, int ns, double tol) {
+__device__ __forceinline__ bool keep_quartet(const PairInfo& P, const PairInfo& Q, const double* dmax_p, int ns,
+                                             double tol) {
     const double qq = P.q * Q.q;
     if (qq < tol) return false;
-    if (dmax == nullptr) return true;
+    if (dmax_p == nullptr) return true;
+    const gptr<const double> dmax = glob(dmax_p);
     const int a = P.sa, b = P.sb, c = Q.sa, d = Q.sb;
     double m = dmax[a * ns + b];
     m = fmax(m, dmax[c * ns + d]);
@@ -198,32 +208,74 @@ __device__ __forceinline__ int find_item(const EriItem* __restrict__ items, int 
     return lo;
 }
 
+// The fields of a primitive pair the recurrences use, in three 16-byte loads.
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ PrimPair load_prim(gptr<const PrimPair> p) {
+    const gptr<const v2d> v = (gptr<const v2d>)p;
+    const v2d a = v[0], b = v[1], c = v[2];
+    PrimPair r;
+    r.p = a.x;
+    r.P[0] = a.y;
+    r.P[1] = b.x;
+    r.P[2] = b.y;
+    r.E = c.x;
+    r.o2p = c.y;
+    r.pad0 = r.pad1 = 0.0;
+    return r;
+}
+
+// A shell pair record, read field by field through a global pointer.
+__device__ __forceinline__ PairInfo load_pair(gptr<const PairInfo> p) {
+    const gptr<const double> d = (gptr<const double>)p;
+    const gptr<const int> n = (gptr<const int>)(d + 7);
+    PairInfo r;
+    r.A[0] = d[0];
+    r.A[1] = d[1];
+    r.A[2] = d[2];
+    r.AB[0] = d[3];
+    r.AB[1] = d[4];
+    r.AB[2] = d[5];
+    r.q = d[6];
+    r.prim_off = n[0];
+    r.nprim = n[1];
+    r.sa = n[2];
+    r.sb = n[3];
+    r.fa = n[4];
+    r.fb = n[5];
+    return r;
+}
+
 // One contracted quartet, one lane.  R = double (FP64 tier) or float (FP32
-// tier; the tile is stored as float).
+// tier: the vertical recurrence per primitive quartet runs in FP32; the
+// contraction over primitives and both horizontal recurrences run in FP64,
+// since the horizontal steps multiply by the pair separations, which are
+// large for exactly the small, distant quartets of this tier; the tile is
+// stored as float).
 template <class C, typename R>
 __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, const EriItem& it, long long q) {
-    const int2 bk = it.quartets[q];
-    const PairInfo& P = m.pairs[bk.x];
-    const PairInfo& Q = m.pairs[bk.y];
+    const long long bkw = glob(reinterpret_cast<const long long*>(it.quartets))[q];   // (bra, ket) pair ids
+    const PairInfo P = load_pair(glob(m.pairs) + static_cast<int>(bkw & 0xffffffff));
+    const PairInfo Q = load_pair(glob(m.pairs) + static_cast<int>(bkw >> 32));
     const long long nq = it.n;
-    R* __restrict__ out = static_cast<R*>(a.tiles) + it.tile_off + q;
+    const gptr<R> out = glob(static_cast<R*>(a.tiles)) + it.tile_off + q;
     if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
         for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
         return;
     }
-    R acc[C::NACC];
+    using C64 = typename C::template With<double>;
+    double acc[C::NACC];
 #pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = R(0);
-    const PrimPair* __restrict__ pb = m.prims + P.prim_off;
-    const PrimPair* __restrict__ pk = m.prims + Q.prim_off;
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    const gptr<const PrimPair> pb = glob(m.prims) + P.prim_off;
+    const gptr<const PrimPair> pk = glob(m.prims) + Q.prim_off;
     const int nb = P.nprim, nk = Q.nprim;
 #pragma unroll 1
     for (int i = 0; i < nb; ++i) {
-        const PrimPair pp = pb[i];
+        const PrimPair pp = load_prim(pb + i);
 #pragma unroll 1
         for (int j = 0; j < nk; ++j) {
-            const PrimPair qq = pk[j];
+            const PrimPair qq = load_prim(pk + j);
             VrrCoef<double> kd;
             double T, pref;
             prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
@@ -238,9 +290,7 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
             }
         }
     }
-    const R AB[3] = {R(P.AB[0]), R(P.AB[1]), R(P.AB[2])};
-    const R CD[3] = {R(Q.AB[0]), R(Q.AB[1]), R(Q.AB[2])};
-    C::hrr(acc, AB, CD, [&](int f, R v) { out[static_cast<long long>(f) * nq] = v; });
+    C64::hrr(acc, P.AB, Q.AB, [&](int f, double v) { out[static_cast<long long>(f) * nq] = static_cast<R>(v); });
 }
 
 // High angular momentum: passes over groups of bra components.  Each pass
@@ -249,20 +299,21 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
 // scratch; HRR-AB then assembles the tile one ket function pair at a time.
 template <class C, typename R, int G>
 __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDesc& m, const PairInfo& P,
-                                               const PairInfo& Q, R* __restrict__ scr, long long nq) {
+                                               const PairInfo& Q, gptr<double> scr, long long nq) {
     if constexpr (G < C::NG) {
-        R acc[C::GMAX];
+        using C64 = typename C::template With<double>;
+        double acc[C::GMAX];
 #pragma unroll
-        for (int i = 0; i < C::GN[G]; ++i) acc[i] = R(0);
-        const PrimPair* __restrict__ pb = m.prims + P.prim_off;
-        const PrimPair* __restrict__ pk = m.prims + Q.prim_off;
+        for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
+        const gptr<const PrimPair> pb = glob(m.prims) + P.prim_off;
+        const gptr<const PrimPair> pk = glob(m.prims) + Q.prim_off;
         const int nb = P.nprim, nk = Q.nprim;
 #pragma unroll 1
         for (int i = 0; i < nb; ++i) {
-            const PrimPair pp = pb[i];
+            const PrimPair pp = load_prim(pb + i);
 #pragma unroll 1
             for (int j = 0; j < nk; ++j) {
-                const PrimPair qq = pk[j];
+                const PrimPair qq = load_prim(pk + j);
                 VrrCoef<double> kd;
                 double T, pref;
                 prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
@@ -277,8 +328,7 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
                 }
             }
         }
-        const R CD[3] = {R(Q.AB[0]), R(Q.AB[1]), R(Q.AB[2])};
-        C::template hrrcd_group<G>(acc, CD, [&](int idx, R v) { scr[static_cast<long long>(idx) * nq] = v; });
+        C64::template hrrcd_group<G>(acc, Q.AB, [&](int idx, double v) { scr[static_cast<long long>(idx) * nq] = v; });
         eri_split_pass<C, R, G + 1>(a, m, P, Q, scr, nq);
     }
 }
@@ -286,23 +336,24 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
 template <class C, typename R>
 __device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDesc& m, const EriItem& it,
                                               long long q) {
-    const int2 bk = it.quartets[q];
-    const PairInfo& P = m.pairs[bk.x];
-    const PairInfo& Q = m.pairs[bk.y];
+    const long long bkw = glob(reinterpret_cast<const long long*>(it.quartets))[q];   // (bra, ket) pair ids
+    const PairInfo P = load_pair(glob(m.pairs) + static_cast<int>(bkw & 0xffffffff));
+    const PairInfo Q = load_pair(glob(m.pairs) + static_cast<int>(bkw >> 32));
     const long long nq = it.n;
-    R* __restrict__ out = static_cast<R*>(a.tiles) + it.tile_off + q;
+    const gptr<R> out = glob(static_cast<R*>(a.tiles)) + it.tile_off + q;
     if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
         for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
         return;
     }
-    R* __restrict__ scr = static_cast<R*>(a.scratch) + it.tile_off + q;
+    // (e0|cd) in FP64 in both tiers: the item's scratch region holds NF x n doubles
+    const gptr<double> scr = glob(static_cast<double*>(a.scratch)) + it.tile_off + q;
     eri_split_pass<C, R, 0>(a, m, P, Q, scr, nq);
-    const R AB[3] = {R(P.AB[0]), R(P.AB[1]), R(P.AB[2])};
+    using C64 = typename C::template With<double>;
 #pragma unroll 1
     for (int cd = 0; cd < C::NCD; ++cd) {
-        C::hrrab([&](int e) -> R { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, AB,
-                 [&](int ab, R v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = v; });
+        C64::hrrab([&](int e) -> double { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, P.AB,
+                   [&](int ab, double v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = static_cast<R>(v); });
     }
 }
 

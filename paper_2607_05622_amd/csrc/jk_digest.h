@@ -35,16 +35,6 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Pointers into device memory reached through descriptors are generic to
-// the compiler; naming them global makes their accesses global (not flat)
-// instructions, whose completion is counted apart from LDS traffic, so
-// loads stay in flight across LDS reads and matrix instructions.
-template <typename T>
-using gptr = T __attribute__((address_space(1)))*;
-template <typename T>
-__device__ __forceinline__ gptr<T> glob(T* p) {
-    return (gptr<T>)p;
-}
 __device__ __forceinline__ void gadd(double* p, double v) { (void)__builtin_amdgcn_global_atomic_fadd_f64(glob(p), v); }
 
 // Workgroup barrier that orders LDS only: the waves' atomics and stores to

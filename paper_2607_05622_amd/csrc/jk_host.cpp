@@ -139,6 +139,13 @@ struct ClassList {
 // pair class X -> (la, lb)
 const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
 
+// Highest total angular momentum la + lb + lc + ld whose quartets may take
+// the FP32 tier.  Beyond it the terms of the FP32 vertical recurrence for
+// distant pairs exceed the integral by more than the FP32 precision buys
+// (measured: d-d classes of the 620-AO workload in FP32 give relative J/K
+// errors of ~5e-6 at a Schwarz bound of 1e-6).
+constexpr int kFp32MaxL = 4;
+
 }  // namespace
 
 namespace {
@@ -323,6 +330,9 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
     for (int X = 0; X < kNumPairClass; ++X) {
         for (int Y = 0; Y <= X; ++Y) {
             const int cls = quartet_class(X, Y);
+            // FP32 tier only for classes of total angular momentum <= kFp32MaxL:
+            // higher classes cancel too strongly in the vertical recurrence
+            const bool fp32_ok = kPairL[X][0] + kPairL[X][1] + kPairL[Y][0] + kPairL[Y][1] <= kFp32MaxL;
             const auto& bra = h->pairs_of_class[X];
             const auto& ket = h->pairs_of_class[Y];
             // ket pairs sorted by Q, descending, to stop early
@@ -341,7 +351,7 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                 }
                 std::sort(keep.begin(), keep.end());
                 for (int k : keep) {
-                    const int t = qb * h->pairs[k].q < bound ? 1 : 0;
+                    const int t = fp32_ok && qb * h->pairs[k].q < bound ? 1 : 0;
                     tier[t].push_back(make_int2(b, k));
                     primq[t] += static_cast<double>(h->pairs[b].nprim) * h->pairs[k].nprim;
                 }
