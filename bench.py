@@ -36,6 +36,83 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+CSRC = os.path.join(ROOT, "paper_2607_05622_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_sources_sha256():
+    """Fingerprint of the kernel sources: measured HBM traffic is valid only
+    for the sources it was taken with."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip", ".cpp", ".py")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def rocprof_name(kernel, g16=True):
+    """The demangled rocprofv3 kernel name of a benchmark kernel name
+    (eri_tile_2111, digest_c_2010, digest_d_fp32_2221, ...)."""
+    parts = kernel.split("_")
+    tag = parts[-1]
+    r = "float" if "fp32" in parts else "double"
+    if kernel.startswith("eri_tile"):
+        return f"void jk::k_eri_tile<jk::Eri{tag}<{r}>, {r}>(jk::EriTileArgs)"
+    return (f"void jk::k_digest_{parts[1]}<{tag[0]}, {tag[1]}, {tag[2]}, {tag[3]}, {r}, "
+            f"{'true' if g16 else 'false'}>(jk::DigestArgs)")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or the kernel sources changed since."""
+    path = os.path.join(PROFILES, f"{kernel}_medium312_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def pmc_summary(fetch_dir, write_dir, kernel, copy_mib, out):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, in KiB per
+    dispatch) of `bench.py --copy-mib N` into HBM bytes per launch of
+    `kernel`, each counter scaled by what it reads for the N-MiB copy."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row["Counter_Name"] == counter:
+                        vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    target = rocprof_name(kernel)
+    res = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        vals = per_kernel(d, counter)
+        copies = [v for k, vs in vals.items() if ("copy" in k.lower() or "elementwise" in k.lower())
+                  for v in vs if v > 0.5 * copy_mib * 1024]
+        if target not in vals or not copies:
+            raise SystemExit(f"{counter}: kernel {target} or the {copy_mib} MiB copy not found in {d}")
+        scale = copy_mib * 1024.0 / (sum(copies) / len(copies))
+        kib = sum(vals[target]) / len(vals[target])
+        res[counter] = {"kib_per_dispatch": kib, "copy_scale": scale, "bytes_per_launch": kib * 1024 * scale,
+                        "dispatches": len(vals[target])}
+    rec = {"kernel": kernel, "rocprof_kernel": target, "source_sha256": kernel_sources_sha256(),
+           "copy_mib": copy_mib, "FETCH_SIZE": res["FETCH_SIZE"], "WRITE_SIZE": res["WRITE_SIZE"],
+           "hbm_bytes_per_launch": res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def workload(name):
     from paper_2607_05622_amd import synth
     if name == "tiny":
@@ -151,7 +228,15 @@ def main():
     ap.add_argument("--rate-low", type=float, default=0.7, help="the same for the latency phase")
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="copy this many MiB on the device before timing (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL"),
+                    help="summarize two rocprofv3 --pmc runs of this script into profiles/")
     args = ap.parse_args()
+    if args.pmc_summary:
+        fd, wd, kern = args.pmc_summary
+        pmc_summary(fd, wd, kern, args.copy_mib, os.path.join(PROFILES, f"{kern}_medium312_traffic.json"))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
@@ -178,6 +263,13 @@ def main():
     J = torch.empty_like(D)
     K = torch.empty_like(D)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def timed(precision):
         opts = jk.jk_default_opts(precision=precision)
@@ -197,7 +289,8 @@ def main():
         ms = ev0.elapsed_time(ev1)
         st = b.stats()
         kernels = []
-        for kind, kname in ((0, "eri_tile"), (1, "digest"), (2, "eri_tile_fp32"), (3, "digest_fp32")):
+        for kind, kname in ((0, "eri_tile"), (1, "digest_c"), (4, "digest_d"), (2, "eri_tile_fp32"),
+                            (3, "digest_c_fp32"), (5, "digest_d_fp32")):
             for c in range(21):
                 r = jk.jk_profile_read(b.h, kind, c)
                 if r["launches"] > 0:
@@ -220,6 +313,9 @@ def main():
     per_launch_flops = dom["flops"] / dom["launches"]
     per_launch_ms = dom["ms"] / dom["launches"]
     achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
+    # digestion runs on the FP64 matrix cores, the integral kernels on the FP64
+    # vector ALUs; MI355X publishes 78.6 TFLOP/s for both
+    dom_bound = "mfma" if dom["kind"].startswith("digest") else "alu"
     builds_s = nd * args.steps / (ms * 1e-3)
     quartets_s = st["quartets"] * args.steps / (ms * 1e-3)
     eri_tflops = sum(r["flops"] for r in kernels if r["kind"].startswith("eri_tile")) / max(tot_eri_ms, 1e-9) / 1e9
@@ -250,12 +346,12 @@ def main():
         "basis_setup_s": setup_s,
         "roofline": {
             "kernel": dom["kernel"],
-            "bound": "alu",
+            "bound": dom_bound,
             "achieved": achieved,
             "peak": FP64_VALU_PEAK,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK,
-            "traffic": None,
+            "traffic": measured_traffic(dom["kernel"]),
             "launches": int(dom["launches"]),
             "mean_launch_ms": per_launch_ms,
             "flops_per_launch": per_launch_flops,

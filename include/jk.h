@@ -182,9 +182,10 @@ int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
  * jk_build on h record a HIP event pair around each integral and digestion
  * launch, on the build's stream; jk_profile_read synchronizes those events
  * and returns, per kernel, totals since the last read, then clears them.
- * kind 0 = integral (ERI tile) kernel, 1 = digestion kernel, 2 and 3 the
- * same for the FP32 tier of JK_MIXED builds; cls = canonical class index
- * 0..20.  out[0] total milliseconds, out[1] launches,
+ * kind 0 = integral (ERI tile) kernel, 1 = digestion pass C (J, and K
+ * over runs of equal ket shell c), 4 = digestion pass D (K over runs of
+ * equal d); 2, 3 and 5 the same for the FP32 tier of JK_MIXED builds;
+ * cls = canonical class index 0..20.  out[0] total milliseconds, out[1] launches,
  * out[2] algorithmic flops, out[3] shell quartets, out[4] bytes written
  * (integral tiles) or read (tiles, digestion).  Not for concurrent builds. */
 int jk_profile_enable(jk_basis_t h, int32_t on);

@@ -193,7 +193,7 @@ struct jk_basis_s {
     };
     bool profiling = false;
     std::vector<ProfRec> prof;
-    double prof_acc[4][kNumClass][5] = {};
+    double prof_acc[6][kNumClass][5] = {};
 
     ~jk_basis_s() {
         int cur = 0;
@@ -472,7 +472,7 @@ struct LaunchRec {
     long long eri_blocks = 0;
     int dig0[2] = {0, 0}, ndig[2] = {0, 0};
     unsigned dig_blocks[2] = {0, 0};
-    double eri_flops = 0, dig_flops = 0, quartets = 0, tile_bytes = 0;
+    double eri_flops = 0, dig_flops[2] = {0, 0}, quartets = 0, tile_bytes = 0;
 };
 
 struct MolRun {
@@ -609,10 +609,15 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     }
                     const double ef = n * (prim_avg * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
                                            kClassCost[c].hrr_flops);
-                    const double df = static_cast<double>(n) * NF * nd *
-                                      (2.0 * (o->want_j ? 2 : 0) + 2.0 * (o->want_k ? 8 : 0));
+                    // pass C: J_ab and J_cd (2 FMA), K_ac and K_bc with D and D^T (4 FMA);
+                    // pass D: K_ad and K_bd with D and D^T (4 FMA) per function quartet and density
+                    const double fq = static_cast<double>(n) * NF * nd;
+                    const double dfc = fq * 2.0 * ((o->want_j ? 2 : 0) + (o->want_k ? 4 : 0));
+                    const double dfd = fq * 2.0 * (o->want_k ? 4 : 0);
+                    const double df = dfc + dfd;
                     L.eri_flops += ef;
-                    L.dig_flops += df;
+                    L.dig_flops[0] += dfc;
+                    L.dig_flops[1] += dfd;
                     L.quartets += n;
                     L.tile_bytes += static_cast<double>(n) * NF * (fp32 ? sizeof(float) : sizeof(double));
                     wp.stats[0] += n;
@@ -945,7 +950,7 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
             da[ps].nblocks = L.ndig[ps] > 0 ? L.dig_blocks[ps] : 0;
         }
         const bool timed = prof && prof->profiling;
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         if (timed) {
             for (auto& x : ev)
                 if (e == hipSuccess) e = hipEventCreate(&x);
@@ -955,13 +960,18 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         e = launch_eri_tile(L.cls, ea, s, L.fp32);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
         if (e == hipSuccess) e = launch_digest(L.cls, da[0], s, L.fp32, 0, L.g16);
-        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[2], s);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[3], s);
         if (e != hipSuccess) return e;
         if (timed) {
             std::lock_guard<std::mutex> g(prof->mu);
             prof->prof.push_back({0 + 2 * L.fp32, L.cls, ev[0], ev[1], L.eri_flops, L.quartets, L.tile_bytes});
-            prof->prof.push_back({1 + 2 * L.fp32, L.cls, ev[1], ev[2], L.dig_flops, L.quartets, L.tile_bytes});
+            prof->prof.push_back({1 + 2 * L.fp32, L.cls, ev[1], ev[2], L.dig_flops[0], L.quartets, L.tile_bytes});
+            if (L.ndig[1] > 0)
+                prof->prof.push_back({4 + L.fp32, L.cls, ev[2], ev[3], L.dig_flops[1], L.quartets, L.tile_bytes});
+            else
+                (void)hipEventDestroy(ev[3]);
         }
     }
     return e;
@@ -1361,7 +1371,7 @@ int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
             if (rc) return rc;
             for (int c = 0; c < kNumClass; ++c) {
                 double tot = 0, v[5];
-                for (int kind = 0; kind < 4; ++kind) {
+                for (int kind = 0; kind < 6; ++kind) {
                     if ((rc = jk_profile_read(h, kind, c, v))) return rc;
                     tot += v[0];
                 }
@@ -1463,7 +1473,7 @@ int jk_profile_enable(jk_basis_t h, int32_t on) {
 }
 
 int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]) {
-    if (!h || !out || kind < 0 || kind > 3 || cls < 0 || cls >= kNumClass)
+    if (!h || !out || kind < 0 || kind > 5 || cls < 0 || cls >= kNumClass)
         return fail(JK_EINVAL, "jk_profile_read: bad arguments");
     std::lock_guard<std::mutex> g(h->mu);
     // fold every pending record into the accumulators; the start event of a
