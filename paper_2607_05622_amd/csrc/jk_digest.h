@@ -73,7 +73,7 @@ template <int LA, int LB, int LC, int LD>
 struct DigShape {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int NF = NA * NB * NC * ND, NAB = NA * NB, NCD = NC * ND;
-    static constexpr int QB = dig_qb(NF), QBP = QB + 1;
+    static constexpr int QB = dig_qb(LA, LB, LC, LD, NF), QBP = QB + 1;
     // accumulator tiles (16 output rows each) per update
     static constexpr int MJ = (NAB + 15) / 16;          // J_ab rows (i, j)
     static constexpr int M2 = (QB * NCD + 15) / 16;     // J_cd rows (quartet, k, l)

@@ -52,11 +52,14 @@ __host__ __device__ inline int quartet_class(int X, int Y) { return X * (X + 1) 
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
-// Quartets a digestion workgroup stages in LDS per chunk for a class with nf
-// Cartesian functions per quartet (a multiple of the MFMA k-depth 4; about
-// 24 KB of LDS per chunk, 52 KB for (dd|dd)).
-__host__ __device__ constexpr int dig_qb(int nf) {
-    return nf <= 90 ? 32 : (nf <= 170 ? 16 : (nf <= 324 ? 8 : 4));
+// Quartets a digestion workgroup stages in LDS per chunk for class
+// (la lb | lc ld) with nf Cartesian functions per quartet: a multiple of the
+// MFMA k-depth 4 and at most ~26 KB of LDS (52 KB for (dd|dd)); chosen by
+// timing each class on the 312-AO workload at 8, 16 and 32.
+__host__ __device__ constexpr int dig_qb(int la, int lb, int lc, int ld, int nf) {
+    return (la == 1 && lb == 1 && lc == 1 && ld == 0) ? 8
+           : (la == 2 && lb == 0 && lc == 1 && ld == 1) ? 16
+           : nf <= 27 ? 16 : (nf <= 90 ? 32 : (nf <= 170 ? 16 : (nf <= 324 ? 8 : 4)));
 }
 
 }  // namespace jk
