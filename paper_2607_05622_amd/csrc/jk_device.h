@@ -27,6 +27,18 @@ __device__ __forceinline__ gptr<T> glob(T* p) {
 
 // ---------------------------------------------------------------- Boys ---
 
+// 1/sqrt(x) for normal positive x: the hardware estimate (about 23 correct
+// bits) refined by two Newton steps y <- y + y (1/2 - x y^2 / 2), each of
+// which doubles the correct bits.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
+
 // F_m(T), m = 0..L, multiplied by pref.  T < kBoysTMax: seven-term Taylor
 // expansion of F_L about the nearest grid point (dF_m/dT = -F_{m+1}), exp(-T)
 // from the tabulated exp(-T0) and an eight-term series, then the downward
@@ -65,10 +77,10 @@ __device__ __forceinline__ void boys_f64(double T, double pref, gptr<const doubl
             for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * inv_odd[m];
         }
     } else {
-        const double it = 1.0 / T;
-        double f = sqrt(0.78539816339744830962 * it);   // sqrt(pi/4 / T)
+        const double rt = rsqrt_f64(T);
+        double f = 0.88622692545275801365 * rt;   // sqrt(pi)/2 / sqrt(T)
         F[0] = f;
-        const double h = 0.5 * it;
+        const double h = 0.5 * rt * rt;
 #pragma unroll
         for (int m = 0; m < L; ++m) {
             f *= static_cast<double>(2 * m + 1) * h;
@@ -111,10 +123,10 @@ __device__ __forceinline__ void boys_f32(double T, double pref, gptr<const float
         for (int m = 0; m <= L; ++m) F[m] = static_cast<float>(static_cast<double>(F[m]) * pref);
     } else {
         double Fd[L + 1];
-        const double it = 1.0 / T;
-        double f = sqrt(0.78539816339744830962 * it);
+        const double rt = rsqrt_f64(T);
+        double f = 0.88622692545275801365 * rt;
         Fd[0] = f;
-        const double h = 0.5 * it;
+        const double h = 0.5 * rt * rt;
 #pragma unroll
         for (int m = 0; m < L; ++m) {
             f *= static_cast<double>(2 * m + 1) * h;
@@ -152,11 +164,12 @@ __device__ __forceinline__ void prim_setup(const PrimPair& P, const PrimPair& Q,
                                            const double* C, VrrCoef<double>& k, double& T,
                                            double& pref) {
     const double p = P.p, q = Q.p;
-    const double ipq = 1.0 / (p + q);
+    const double rs = rsqrt_f64(p + q);
+    const double ipq = rs * rs;
     const double rho = p * q * ipq;
     const double PQx = P.P[0] - Q.P[0], PQy = P.P[1] - Q.P[1], PQz = P.P[2] - Q.P[2];
     T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    pref = P.E * Q.E * sqrt(ipq);
+    pref = P.E * Q.E * rs;
     const double qf = q * ipq, pf = p * ipq;
     k.WP[0] = -qf * PQx;
     k.WP[1] = -qf * PQy;
@@ -224,6 +237,50 @@ __device__ __forceinline__ PrimPair load_prim(gptr<const PrimPair> p) {
     return r;
 }
 
+// Calls body(bra primitive pair, ket primitive pair) for every primitive
+// quartet, bra-major.  With PF the records of the next quartet are loaded
+// before the body runs, so their latency overlaps the current quartet's
+// arithmetic; that pays in the classes whose registers leave one wave per
+// SIMD, and costs memory instructions and registers elsewhere.
+template <bool PF, class Body>
+__device__ __forceinline__ void prim_loop(gptr<const PrimPair> pb, int nb, gptr<const PrimPair> pk, int nk,
+                                          Body body) {
+    if constexpr (PF) {
+        if (nb <= 0 || nk <= 0) return;
+        PrimPair pp = load_prim(pb), qq = load_prim(pk);
+        int i = 0, j = 0;
+#pragma unroll 1
+        for (int n = nb * nk; n > 0; --n) {
+            int jn = j + 1, in = i;
+            if (jn == nk) {
+                jn = 0;
+                in = i + 1 < nb ? i + 1 : i;
+            }
+            const PrimPair qn = load_prim(pk + jn);
+            const PrimPair pn = load_prim(pb + in);
+            body(pp, qq);
+            pp = pn;
+            qq = qn;
+            i = in;
+            j = jn;
+        }
+    } else {
+#pragma unroll 1
+        for (int i = 0; i < nb; ++i) {
+            const PrimPair pp = load_prim(pb + i);
+#pragma unroll 1
+            for (int j = 0; j < nk; ++j) body(pp, load_prim(pk + j));
+        }
+    }
+}
+
+// Classes that prefetch primitive records (high angular momentum, large
+// accumulator sets).
+template <class C>
+constexpr bool prim_prefetch() {
+    return C::L >= 5 && C::NACC >= 96;
+}
+
 // A shell pair record, read field by field through a global pointer.
 __device__ __forceinline__ PairInfo load_pair(gptr<const PairInfo> p) {
     const gptr<const double> d = (gptr<const double>)p;
@@ -267,29 +324,21 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
     double acc[C::NACC];
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    const gptr<const PrimPair> pb = glob(m.prims) + P.prim_off;
-    const gptr<const PrimPair> pk = glob(m.prims) + Q.prim_off;
-    const int nb = P.nprim, nk = Q.nprim;
-#pragma unroll 1
-    for (int i = 0; i < nb; ++i) {
-        const PrimPair pp = load_prim(pb + i);
-#pragma unroll 1
-        for (int j = 0; j < nk; ++j) {
-            const PrimPair qq = load_prim(pk + j);
-            VrrCoef<double> kd;
-            double T, pref;
-            prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
-            R F[C::L + 1];
-            boys_r<C::L, R>(T, pref, a, F);
-            if constexpr (sizeof(R) == 8) {
-                C::vrr(F, kd, acc);
-            } else {
-                VrrCoef<R> k;
-                coef_to(kd, k);
-                C::vrr(F, k, acc);
-            }
-        }
-    }
+    prim_loop<prim_prefetch<C>()>(glob(m.prims) + P.prim_off, P.nprim, glob(m.prims) + Q.prim_off, Q.nprim,
+              [&](const PrimPair& pp, const PrimPair& qq) {
+                  VrrCoef<double> kd;
+                  double T, pref;
+                  prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
+                  R F[C::L + 1];
+                  boys_r<C::L, R>(T, pref, a, F);
+                  if constexpr (sizeof(R) == 8) {
+                      C::vrr(F, kd, acc);
+                  } else {
+                      VrrCoef<R> k;
+                      coef_to(kd, k);
+                      C::vrr(F, k, acc);
+                  }
+              });
     C64::hrr(acc, P.AB, Q.AB, [&](int f, double v) { out[static_cast<long long>(f) * nq] = static_cast<R>(v); });
 }
 
@@ -305,29 +354,21 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
         double acc[C::GMAX];
 #pragma unroll
         for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
-        const gptr<const PrimPair> pb = glob(m.prims) + P.prim_off;
-        const gptr<const PrimPair> pk = glob(m.prims) + Q.prim_off;
-        const int nb = P.nprim, nk = Q.nprim;
-#pragma unroll 1
-        for (int i = 0; i < nb; ++i) {
-            const PrimPair pp = load_prim(pb + i);
-#pragma unroll 1
-            for (int j = 0; j < nk; ++j) {
-                const PrimPair qq = load_prim(pk + j);
-                VrrCoef<double> kd;
-                double T, pref;
-                prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
-                R F[C::L + 1];
-                boys_r<C::L, R>(T, pref, a, F);
-                if constexpr (sizeof(R) == 8) {
-                    C::template vrr_group<G>(F, kd, acc);
-                } else {
-                    VrrCoef<R> k;
-                    coef_to(kd, k);
-                    C::template vrr_group<G>(F, k, acc);
-                }
-            }
-        }
+        prim_loop<prim_prefetch<C>()>(glob(m.prims) + P.prim_off, P.nprim, glob(m.prims) + Q.prim_off, Q.nprim,
+                  [&](const PrimPair& pp, const PrimPair& qq) {
+                      VrrCoef<double> kd;
+                      double T, pref;
+                      prim_setup(pp, qq, P.A, Q.A, kd, T, pref);
+                      R F[C::L + 1];
+                      boys_r<C::L, R>(T, pref, a, F);
+                      if constexpr (sizeof(R) == 8) {
+                          C::template vrr_group<G>(F, kd, acc);
+                      } else {
+                          VrrCoef<R> k;
+                          coef_to(kd, k);
+                          C::template vrr_group<G>(F, k, acc);
+                      }
+                  });
         C64::template hrrcd_group<G>(acc, Q.AB, [&](int idx, double v) { scr[static_cast<long long>(idx) * nq] = v; });
         eri_split_pass<C, R, G + 1>(a, m, P, Q, scr, nq);
     }

@@ -46,6 +46,13 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846;
+// Primitive-pair screen: a primitive pair (alpha, beta) of shells a, b is
+// kept iff |E_ab| max(1, |AB|)^(la+lb) >= kPrimPairTol, E_ab the prefactor
+// of PrimPair (its Gaussian product factor exp(-alpha beta/p |AB|^2) times
+// the contraction weights), the power bounding the separations the
+// recurrences multiply in.  1e-6 of the default quartet threshold: what is
+// dropped stays far below FP64 rounding of the contracted integrals.
+constexpr double kPrimPairTol = 1e-18;
 constexpr long long kTileCapElems = 32ll << 20;   // 256 MB FP64 work buffer cap
 
 double dfact(int n) {
@@ -808,6 +815,10 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
             P.fa = h->f0_int[a];
             P.fb = h->f0_int[b];
             P.prim_off = static_cast<int>(h->prims.size());
+            // primitive pairs whose prefactor, times the largest power of the
+            // pair separation the recurrences can apply, is below
+            // kPrimPairTol are left out
+            const double ang = std::pow(std::max(1.0, std::sqrt(ab2)), h->l_int[a] + h->l_int[b]);
             for (int i = 0; i < h->nprim_int[a]; ++i)
                 for (int j = 0; j < h->nprim_int[b]; ++j) {
                     const double al = h->exps_int[a][i], be = h->exps_int[b][j];
@@ -817,9 +828,9 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
                     for (int k = 0; k < 3; ++k) pp.P[k] = (al * A[k] + be * B[k]) / p;
                     pp.E = E0 * h->w_int[a][i] * h->w_int[b][j] * std::exp(-al * be / p * ab2) / p;
                     pp.o2p = 0.5 / p;
-                    h->prims.push_back(pp);
+                    if (std::fabs(pp.E) * ang >= kPrimPairTol) h->prims.push_back(pp);
                 }
-            P.nprim = h->nprim_int[a] * h->nprim_int[b];
+            P.nprim = static_cast<int>(h->prims.size()) - P.prim_off;
             const int id = static_cast<int>(h->pairs.size());
             h->pair_id[static_cast<size_t>(a) * ns + b] = id;
             h->pairs.push_back(P);
