@@ -127,7 +127,9 @@ size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t
 
 /* Schedule autotuning.  Per canonical class the library keeps two launch
  * parameters: seg_max, the length cap of a digestion piece (quartets of one
- * bra pair digested by one wave), and g_max, the densities a digestion wave
+ * bra pair digested by one workgroup: a run of equal ket shell, cut at the
+ * cap; classes of at most 18 functions per quartet pack consecutive runs up
+ * to the cap), and g_max, the densities a digestion wave
  * takes at once (16; any of 1, 2, 4, 8 selects 8, which is also used when
  * a build has at most 8 densities).  jk_autotune times
  * every candidate pair on the given build with the event profiler, keeps

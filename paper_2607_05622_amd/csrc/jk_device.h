@@ -25,6 +25,30 @@ __device__ __forceinline__ gptr<T> glob(T* p) {
     return (gptr<T>)p;
 }
 
+// The descriptor of molecule i of a batch (or mol0 for a single build),
+// copied into registers.  Read through a reference, its fields would be
+// reloaded after every store or atomic the kernel issues (the compiler
+// cannot rule out that they alias it), and each reload waits for those to
+// complete.
+__device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& mol0, int i) {
+    if (!mols) return mol0;
+    const gptr<const unsigned long long> w = (gptr<const unsigned long long>)(mols + i);
+    const gptr<const int> n = (gptr<const int>)(w + 7);
+    MolDesc m;
+    m.pairs = reinterpret_cast<const PairInfo*>(w[0]);
+    m.prims = reinterpret_cast<const PrimPair*>(w[1]);
+    m.dmax = reinterpret_cast<const double*>(w[2]);
+    m.D = reinterpret_cast<const double*>(w[3]);
+    m.J = reinterpret_cast<double*>(w[4]);
+    m.K = reinterpret_cast<double*>(w[5]);
+    m.KT = reinterpret_cast<double*>(w[6]);
+    m.ns = n[0];
+    m.nc = n[1];
+    m.nd = n[2];
+    m.ndp = n[3];
+    return m;
+}
+
 // ---------------------------------------------------------------- Boys ---
 
 // 1/sqrt(x) for normal positive x: the hardware estimate (about 23 correct
@@ -406,7 +430,7 @@ __global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
         const EriItem it = a.items[find_item(a.items, a.nitems, blk)];
         const long long q = (blk - it.blk0) * blockDim.x + threadIdx.x;
         if (q >= it.n) continue;
-        const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
+        const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
         if constexpr (C::kSplit) eri_one_split<C, R>(a, m, it, q);
         else eri_one<C, R>(a, m, it, q);
     }

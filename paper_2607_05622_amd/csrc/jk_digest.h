@@ -167,7 +167,7 @@ __global__ __launch_bounds__(192) void k_digest_c(DigestArgs a) {
     const DigItem it = *itp;
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
-    const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
+    const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
     const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 2 : c16 >= 8);
     const long long nc = m.nc;
     const PairInfo& P = m.pairs[it.bra];
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(128) void k_digest_d(DigestArgs a) {
     const DigItem it = *itp;
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
-    const MolDesc& m = a.mols ? a.mols[it.mol] : a.mol0;
+    const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
     const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 1 : c16 >= 8);
     const PairInfo& P = m.pairs[it.bra];
     const int fa = P.fa, fb = P.fb;

@@ -134,7 +134,8 @@ struct ClassList {
     std::vector<int2> blocks;        // (first quartet, count)
     std::vector<int> block_bra;      // bra shell pair of each block
     // digestion parts per pass (0: runs of equal c in list order, 1: runs of
-    // equal d in (d, c) order, cut at the tunable cap): block k's parts start
+    // equal d in (d, c) order, packed whole up to the tunable cap, longer
+    // runs cut at it): block k's parts start
     // at positions parts[ps][part_off[ps][k] ..] of the block
     std::vector<int> part_off[2];
     int* dev_parts[2] = {nullptr, nullptr};
@@ -375,6 +376,7 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             std::vector<int> pos(out.size()), idx, parts[2];
             std::vector<int2> kin(out.size()), kind(out.size());
             const int cap = std::max(4, tune_of(cls).seg_max);
+            const bool pack = kClassCost[cls].nfunc <= 18;
             for (size_t q = 0; q < out.size(); ++q) {
                 const PairInfo& Q = h->pairs[out[q].y];
                 kin[q] = make_int2(Q.sa | (Q.sb << 16), Q.fa | (Q.fb << 16));
@@ -397,17 +399,34 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                         kind[q + p] = kin[q + idx[p]];
                         pos[q + idx[p]] = static_cast<int>(p);
                     }
-                    // parts: runs of equal c (pass C) and of equal d (pass D)
+                    // parts: runs of equal c (pass C) or d (pass D), a run
+                    // longer than cap cut into pieces of cap.  Classes of at
+                    // most 18 functions per quartet pack consecutive whole
+                    // runs into one part up to cap positions: their runs are
+                    // short and a workgroup's set-up outweighs its work.
                     for (int ps = 0; ps < 2; ++ps) {
                         const std::vector<int2>& kv = ps ? kind : kin;
                         const int shift = ps ? 16 : 0;
+                        const size_t ucap = static_cast<size_t>(cap), none = ~size_t(0);
                         F.part_off[ps].push_back(static_cast<int>(parts[ps].size()));
+                        size_t open = none;   // first position of the part being filled
                         for (size_t p = q; p < e;) {
                             size_t r = p + 1;
                             while (r < e && ((kv[r].x >> shift) & 0xffff) == ((kv[p].x >> shift) & 0xffff)) ++r;
-                            for (size_t c = p; c < r; c += cap) parts[ps].push_back(static_cast<int>(c - q));
+                            if (r - p > ucap) {
+                                if (open != none) parts[ps].push_back(static_cast<int>(open - q));
+                                open = none;
+                                for (size_t c = p; c < r; c += ucap) parts[ps].push_back(static_cast<int>(c - q));
+                            } else {
+                                if (open != none && (!pack || r - open > ucap)) {
+                                    parts[ps].push_back(static_cast<int>(open - q));
+                                    open = none;
+                                }
+                                if (open == none) open = p;
+                            }
                             p = r;
                         }
+                        if (open != none) parts[ps].push_back(static_cast<int>(open - q));
                     }
                     q = e;
                 }

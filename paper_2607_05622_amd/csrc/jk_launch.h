@@ -37,6 +37,9 @@ struct MolDesc {
     double* KT;             // exchange, transposed contributions (K += KT^T at the end)
     int ns, nc, nd, ndp;
 };
+// load_mol reads the fields at these offsets
+static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ns) == 56 && sizeof(MolDesc) == 72,
+              "MolDesc layout");
 
 // A contiguous run of one molecule's class list whose tiles occupy
 // [tile_off, tile_off + NF * n) of the work buffer, layout [NF][n].
@@ -65,9 +68,10 @@ struct EriTileArgs {
 // class and tier, consecutive in the class list with ket pairs in (c, d)
 // order).  Its tasks, one workgroup each, are its parts times the density
 // groups of 8 or 16: task kstart + pc * ngroups + g digests part pc for
-// group g.  Pass C walks the block in list order and its parts are the runs
-// of equal ket shell c; pass D walks the order sorted by (d, c) and its parts
-// are the runs of equal d (runs longer than a cap are cut).  Blocks are dealt to the XCDs: item i of a launch belongs to XCD
+// group g.  Pass C walks the block in list order and its parts are runs of
+// equal ket shell c; pass D walks the order sorted by (d, c) and its parts
+// are runs of equal d (runs longer than a cap are cut; classes with few
+// functions per quartet pack consecutive runs up to the cap).  Blocks are dealt to the XCDs: item i of a launch belongs to XCD
 // i % 8, whose tasks are numbered from 0 in item order (idle padding items
 // have kstart = INT_MAX).
 struct DigItem {
