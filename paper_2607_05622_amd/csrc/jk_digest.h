@@ -74,6 +74,7 @@ struct DigShape {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int NF = NA * NB * NC * ND, NAB = NA * NB, NCD = NC * ND;
     static constexpr int QB = dig_qb(LA, LB, LC, LD, NF), QBP = QB + 1;
+    static constexpr int WAVES_C = dig_waves_c(LA, LB, LC, LD), WAVES_D = 3;
     // accumulator tiles (16 output rows each) per update
     static constexpr int MJ = (NAB + 15) / 16;          // J_ab rows (i, j)
     static constexpr int M2 = (QB * NCD + 15) / 16;     // J_cd rows (quartet, k, l)
@@ -152,7 +153,8 @@ __device__ __forceinline__ int dig_chunk(gptr<const long long> kin, int p, int p
 // Pass C: J_ab, J_cd (wave 0), K_ac, K_bc (the other waves) over runs of
 // equal ket shell c, and the D-order copy of the tiles for pass D.
 template <int LA, int LB, int LC, int LD, typename TT, bool G16>
-__global__ __launch_bounds__(192) void k_digest_c(DigestArgs a) {
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(DigShape<LA, LB, LC, LD>::WAVES_C)))
+void k_digest_c(DigestArgs a) {
     using S = DigShape<LA, LB, LC, LD>;
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NAB = S::NAB, NCD = S::NCD;
     constexpr int QB = S::QB, QBP = S::QBP;
@@ -353,7 +355,8 @@ __global__ __launch_bounds__(192) void k_digest_c(DigestArgs a) {
 // Pass D: K_ad and K_bd over runs of equal ket shell d, from the D-order
 // copy; one wave per K contraction (D, and D^T when 16 densities).
 template <int LA, int LB, int LC, int LD, typename TT, bool G16>
-__global__ __launch_bounds__(128) void k_digest_d(DigestArgs a) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(DigShape<LA, LB, LC, LD>::WAVES_D)))
+void k_digest_d(DigestArgs a) {
     using S = DigShape<LA, LB, LC, LD>;
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NCD = S::NCD;
     constexpr int QB = S::QB, QBP = S::QBP;

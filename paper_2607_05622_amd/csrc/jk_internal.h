@@ -62,4 +62,16 @@ __host__ __device__ constexpr int dig_qb(int la, int lb, int lc, int ld, int nf)
            : nf <= 27 ? 16 : (nf <= 90 ? 32 : (nf <= 170 ? 16 : (nf <= 324 ? 8 : 4)));
 }
 
+// Minimum waves per SIMD the digestion kernels of class (la lb | lc ld) are
+// compiled for (pass C; pass D uses 3): the register budget that trades
+// spills against latency hiding, chosen by timing each class on the 312-AO
+// workload at 1 to 4.
+__host__ __device__ constexpr int dig_waves_c(int la, int lb, int lc, int ld) {
+    const int t = la * 1000 + lb * 100 + lc * 10 + ld;
+    return (t == 1111 || t == 2221) ? 1
+           : (t == 2020 || t == 2111 || t == 2120 || t == 2121 || t == 2211) ? 3
+           : (t == 1110 || t == 2000) ? 4
+           : 2;
+}
+
 }  // namespace jk
