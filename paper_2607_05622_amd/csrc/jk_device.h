@@ -36,7 +36,7 @@ __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& 
     const gptr<const int> n = (gptr<const int>)(w + 7);
     MolDesc m;
     m.pairs = reinterpret_cast<const PairInfo*>(w[0]);
-    m.prims = reinterpret_cast<const PrimPair*>(w[1]);
+    m.prims = reinterpret_cast<const double*>(w[1]);
     m.dmax = reinterpret_cast<const double*>(w[2]);
     m.D = reinterpret_cast<const double*>(w[3]);
     m.J = reinterpret_cast<double*>(w[4]);
@@ -46,6 +46,8 @@ __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& 
     m.nc = n[1];
     m.nd = n[2];
     m.ndp = n[3];
+    m.pslots = n[4];
+    m.pad = 0;
     return m;
 }
 
@@ -245,33 +247,35 @@ __device__ __forceinline__ int find_item(const EriItem* __restrict__ items, int 
     return lo;
 }
 
-// The fields of a primitive pair the recurrences use, in three 16-byte loads.
+// The primitive-pair record in slot `slot` of the planes at pl (pslots
+// entries each), in three 16-byte loads.
 typedef double v2d __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ PrimPair load_prim(gptr<const PrimPair> p) {
-    const gptr<const v2d> v = (gptr<const v2d>)p;
-    const v2d a = v[0], b = v[1], c = v[2];
+__device__ __forceinline__ PrimPair load_prim(gptr<const v2d> pl, long long pslots, int slot) {
+    const v2d a = pl[slot], b = pl[pslots + slot], c = pl[2 * pslots + slot];
     PrimPair r;
     r.p = a.x;
-    r.P[0] = a.y;
-    r.P[1] = b.x;
-    r.P[2] = b.y;
-    r.E = c.x;
+    r.E = a.y;
+    r.P[0] = b.x;
+    r.P[1] = b.y;
+    r.P[2] = c.x;
     r.o2p = c.y;
     r.pad0 = r.pad1 = 0.0;
     return r;
 }
 
 // Calls body(bra primitive pair, ket primitive pair) for every primitive
-// quartet, bra-major.  With PF the records of the next quartet are loaded
+// quartet, bra-major; a pair's records start in slot b0 (bra) or k0 (ket),
+// kPrimLane apart.  With PF the records of the next quartet are loaded
 // before the body runs, so their latency overlaps the current quartet's
 // arithmetic; that pays in the classes whose registers leave one wave per
 // SIMD, and costs memory instructions and registers elsewhere.
 template <bool PF, class Body>
-__device__ __forceinline__ void prim_loop(gptr<const PrimPair> pb, int nb, gptr<const PrimPair> pk, int nk,
-                                          Body body) {
+__device__ __forceinline__ void prim_loop(const MolDesc& m, int b0, int nb, int k0, int nk, Body body) {
+    const gptr<const v2d> pl = glob(reinterpret_cast<const v2d*>(m.prims));
+    const long long ps = m.pslots;
     if constexpr (PF) {
         if (nb <= 0 || nk <= 0) return;
-        PrimPair pp = load_prim(pb), qq = load_prim(pk);
+        PrimPair pp = load_prim(pl, ps, b0), qq = load_prim(pl, ps, k0);
         int i = 0, j = 0;
 #pragma unroll 1
         for (int n = nb * nk; n > 0; --n) {
@@ -280,8 +284,8 @@ __device__ __forceinline__ void prim_loop(gptr<const PrimPair> pb, int nb, gptr<
                 jn = 0;
                 in = i + 1 < nb ? i + 1 : i;
             }
-            const PrimPair qn = load_prim(pk + jn);
-            const PrimPair pn = load_prim(pb + in);
+            const PrimPair qn = load_prim(pl, ps, k0 + kPrimLane * jn);
+            const PrimPair pn = load_prim(pl, ps, b0 + kPrimLane * in);
             body(pp, qq);
             pp = pn;
             qq = qn;
@@ -291,9 +295,9 @@ __device__ __forceinline__ void prim_loop(gptr<const PrimPair> pb, int nb, gptr<
     } else {
 #pragma unroll 1
         for (int i = 0; i < nb; ++i) {
-            const PrimPair pp = load_prim(pb + i);
+            const PrimPair pp = load_prim(pl, ps, b0 + kPrimLane * i);
 #pragma unroll 1
-            for (int j = 0; j < nk; ++j) body(pp, load_prim(pk + j));
+            for (int j = 0; j < nk; ++j) body(pp, load_prim(pl, ps, k0 + kPrimLane * j));
         }
     }
 }
@@ -348,7 +352,7 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
     double acc[C::NACC];
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    prim_loop<prim_prefetch<C>()>(glob(m.prims) + P.prim_off, P.nprim, glob(m.prims) + Q.prim_off, Q.nprim,
+    prim_loop<prim_prefetch<C>()>(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
               [&](const PrimPair& pp, const PrimPair& qq) {
                   VrrCoef<double> kd;
                   double T, pref;
@@ -378,7 +382,7 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
         double acc[C::GMAX];
 #pragma unroll
         for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
-        prim_loop<prim_prefetch<C>()>(glob(m.prims) + P.prim_off, P.nprim, glob(m.prims) + Q.prim_off, Q.nprim,
+        prim_loop<prim_prefetch<C>()>(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
                   [&](const PrimPair& pp, const PrimPair& qq) {
                       VrrCoef<double> kd;
                       double T, pref;
@@ -422,10 +426,21 @@ __device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDes
     }
 }
 
+// Minimum waves per SIMD an integral kernel is compiled for: 2 where timing
+// the classes at 1 to 8 showed a gain ((ds|ds) and (dp|ds)); elsewhere the
+// register allocation the compiler picks is fastest.
+template <class C>
+constexpr int eri_waves() {
+    return (C::LA == 2 && C::LB == 0 && C::LC == 2 && C::LD == 0) ||
+                   (C::LA == 2 && C::LB == 1 && C::LC == 2 && C::LD == 0)
+               ? 2
+               : 1;
+}
+
 // Grid-stride over the blocks of every item of the launch (all molecules of
 // a batch for one class and tier).
 template <class C, typename R>
-__global__ __launch_bounds__(256) void k_eri_tile(EriTileArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(eri_waves<C>()))) void k_eri_tile(EriTileArgs a) {
     for (long long blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
         const EriItem it = a.items[find_item(a.items, a.nitems, blk)];
         const long long q = (blk - it.blk0) * blockDim.x + threadIdx.x;

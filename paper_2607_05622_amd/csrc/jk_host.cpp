@@ -170,12 +170,14 @@ struct jk_basis_s {
     std::vector<double> centre_int;   // [ns][3]
     std::vector<std::vector<double>> exps_int, w_int;   // normalized contraction weights
     std::vector<PairInfo> pairs;
-    std::vector<PrimPair> prims;
+    std::vector<PrimPair> prims;          // set-up only: records, pair-major
+    std::vector<double> prim_planes;      // set-up only: their device layout (kPrimLane)
+    int pslots = 0;
     std::vector<int> pair_id;   // [ns][ns] -> pair index for a >= b, else -1
     std::vector<int> pairs_of_class[kNumPairClass];
     // device
     PairInfo* d_pairs = nullptr;
-    PrimPair* d_prims = nullptr;
+    double* d_prims = nullptr;
     double* d_boys = nullptr;
     CartMap* d_cmap = nullptr;
     UserMap* d_umap = nullptr;
@@ -276,6 +278,7 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
         a.nblocks = (nq + 255) / 256;
         a.mol0.pairs = h->d_pairs;
         a.mol0.prims = h->d_prims;
+        a.mol0.pslots = h->pslots;
         a.mol0.dmax = nullptr;
         a.mol0.ns = h->ns;
         a.mols = nullptr;
@@ -856,6 +859,42 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
             h->pairs_of_class[pair_class(h->l_int[a], h->l_int[b])].push_back(id);
         }
     }
+    // device layout of the primitive-pair records: groups of kPrimLane
+    // consecutive pair ids, record j of every pair of a group side by side
+    {
+        const int npair = static_cast<int>(h->pairs.size());
+        std::vector<long long> slot0(npair);
+        long long nslot = 0;
+        for (int g0 = 0; g0 < npair; g0 += kPrimLane) {
+            const int g1 = std::min(npair, g0 + kPrimLane);
+            int mx = 0;
+            for (int i = g0; i < g1; ++i) {
+                mx = std::max(mx, h->pairs[i].nprim);
+                slot0[i] = nslot + (i - g0);
+            }
+            nslot += static_cast<long long>(kPrimLane) * mx;
+        }
+        if (nslot > (1ll << 30))
+            return fail(JK_EUNSUPPORTED, "jk_create_basis: %lld primitive-pair slots (at most 2^30)", nslot);
+        h->pslots = static_cast<int>(nslot);
+        h->prim_planes.assign(static_cast<size_t>(6 * nslot), 0.0);
+        double* pl = h->prim_planes.data();
+        for (int i = 0; i < npair; ++i) {
+            PairInfo& P = h->pairs[i];
+            for (int j = 0; j < P.nprim; ++j) {
+                const PrimPair& r = h->prims[static_cast<size_t>(P.prim_off) + j];
+                const long long sl = slot0[i] + static_cast<long long>(kPrimLane) * j;
+                pl[2 * sl] = r.p;
+                pl[2 * sl + 1] = r.E;
+                pl[2 * (nslot + sl)] = r.P[0];
+                pl[2 * (nslot + sl) + 1] = r.P[1];
+                pl[2 * (2 * nslot + sl)] = r.P[2];
+                pl[2 * (2 * nslot + sl) + 1] = r.o2p;
+            }
+            P.prim_off = static_cast<int>(slot0[i]);
+        }
+        std::vector<PrimPair>().swap(h->prims);
+    }
 
     // basis-change maps
     std::vector<CartMap> cmap(h->nc);
@@ -899,7 +938,8 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     std::vector<int> sf0(h->f0_int.begin(), h->f0_int.begin() + ns);
     int rc;
     if ((rc = upload(&h->d_pairs, h->pairs))) return rc;
-    if ((rc = upload(&h->d_prims, h->prims))) return rc;
+    if ((rc = upload(&h->d_prims, h->prim_planes))) return rc;
+    std::vector<double>().swap(h->prim_planes);
     if ((rc = upload(&h->d_boys, boys_table()))) return rc;
     {
         std::vector<float> t32(boys_table().begin(), boys_table().end());
@@ -1068,6 +1108,7 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     if (e == hipSuccess && KTc) e = launch_zero(KTc, mat, s);
     md.pairs = h->d_pairs;
     md.prims = h->d_prims;
+    md.pslots = h->pslots;
     md.dmax = dmax;
     md.D = Dc;
     md.J = Jc;

@@ -23,7 +23,7 @@ struct PairInfo {
     double A[3];      // centre of a
     double AB[3];     // A - B
     double q;         // Schwarz factor sqrt(max (mn|mn))
-    int32_t prim_off; // first primitive-pair record
+    int32_t prim_off; // slot of the first primitive-pair record (record j in slot prim_off + kPrimLane j)
     int32_t nprim;    // number of primitive-pair records
     int32_t sa, sb;   // internal shells
     int32_t fa, fb;   // first internal Cartesian function of a, b
@@ -36,6 +36,14 @@ struct PairInfo {
 struct PrimPair {
     double p, P[3], E, o2p, pad0, pad1;
 };
+
+// Device layout of the primitive-pair records: three planes of pslots
+// (2 x double) entries, (p, E), (P_x, P_y), (P_z, 1/2p).  The pairs are
+// taken in groups of kPrimLane consecutive pair ids; record j of pair i sits
+// in slot base(i / kPrimLane) + kPrimLane j + i % kPrimLane, so the lanes of
+// a wavefront reading record j of consecutive ket pairs read consecutive
+// entries.
+constexpr int kPrimLane = 64;
 
 // Per-primitive-quartet coefficients of the vertical recurrence.
 template <typename R>

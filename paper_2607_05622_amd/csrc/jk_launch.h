@@ -29,16 +29,18 @@ struct UserMap {
 // the density count rounded up to the digestion group (zero beyond nd).
 struct MolDesc {
     const PairInfo* pairs;
-    const PrimPair* prims;
+    const double* prims;    // primitive-pair planes (layout at kPrimLane)
     const double* dmax;     // [ns][ns] or nullptr (no density screen)
     const double* D;        // Cartesian densities
     double* J;              // Coulomb accumulator (J = Jc + Jc^T at the end)
     double* K;              // exchange, row contributions K[a][c]
     double* KT;             // exchange, transposed contributions (K += KT^T at the end)
     int ns, nc, nd, ndp;
+    int pslots, pad;        // entries per primitive-pair plane
 };
 // load_mol reads the fields at these offsets
-static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ns) == 56 && sizeof(MolDesc) == 72,
+static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ns) == 56 &&
+                  __builtin_offsetof(MolDesc, pslots) == 72 && sizeof(MolDesc) == 80,
               "MolDesc layout");
 
 // A contiguous run of one molecule's class list whose tiles occupy
