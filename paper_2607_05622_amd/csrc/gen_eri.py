@@ -235,6 +235,10 @@ class Emitter:
 # tile one ket function pair at a time.
 SPLIT_NACC = 40
 TARGET_BUDGET = 32
+# per-class budgets where timing on MI355X preferred fewer, larger passes
+# (fewer repeats of the primitive set-up and Boys evaluation)
+CLASS_BUDGET = {(1, 1, 1, 1): 96, (2, 0, 1, 1): 64, (2, 1, 1, 0): 64, (2, 1, 1, 1): 96, (2, 2, 1, 0): 96,
+                (2, 2, 1, 1): 64, (2, 2, 2, 0): 64, (2, 2, 2, 1): 64, (2, 2, 2, 2): 64}
 
 
 def split_plan(em, info):
@@ -242,7 +246,8 @@ def split_plan(em, info):
     leaves = info["leaves"]
     es = sorted({e for e, f in leaves}, key=lambda e: (sum(e), e))
     fs = sorted({f for e, f in leaves}, key=lambda f: (sum(f), f))
-    per = max(1, TARGET_BUDGET // len(fs))
+    budget = CLASS_BUDGET.get((em.la, em.lb, em.lc, em.ld), TARGET_BUDGET)
+    per = max(1, budget // len(fs))
     groups = [es[i:i + per] for i in range(0, len(es), per)]
     return es, fs, groups
 
