@@ -265,48 +265,18 @@ __device__ __forceinline__ PrimPair load_prim(gptr<const v2d> pl, long long pslo
 
 // Calls body(bra primitive pair, ket primitive pair) for every primitive
 // quartet, bra-major; a pair's records start in slot b0 (bra) or k0 (ket),
-// kPrimLane apart.  With PF the records of the next quartet are loaded
-// before the body runs, so their latency overlaps the current quartet's
-// arithmetic; that pays in the classes whose registers leave one wave per
-// SIMD, and costs memory instructions and registers elsewhere.
-template <bool PF, class Body>
+// kPrimLane apart.  (Loading the next quartet's records ahead of the body
+// stopped paying once the ket records were laid out for coalesced loads.)
+template <class Body>
 __device__ __forceinline__ void prim_loop(const MolDesc& m, int b0, int nb, int k0, int nk, Body body) {
     const gptr<const v2d> pl = glob(reinterpret_cast<const v2d*>(m.prims));
     const long long ps = m.pslots;
-    if constexpr (PF) {
-        if (nb <= 0 || nk <= 0) return;
-        PrimPair pp = load_prim(pl, ps, b0), qq = load_prim(pl, ps, k0);
-        int i = 0, j = 0;
 #pragma unroll 1
-        for (int n = nb * nk; n > 0; --n) {
-            int jn = j + 1, in = i;
-            if (jn == nk) {
-                jn = 0;
-                in = i + 1 < nb ? i + 1 : i;
-            }
-            const PrimPair qn = load_prim(pl, ps, k0 + kPrimLane * jn);
-            const PrimPair pn = load_prim(pl, ps, b0 + kPrimLane * in);
-            body(pp, qq);
-            pp = pn;
-            qq = qn;
-            i = in;
-            j = jn;
-        }
-    } else {
+    for (int i = 0; i < nb; ++i) {
+        const PrimPair pp = load_prim(pl, ps, b0 + kPrimLane * i);
 #pragma unroll 1
-        for (int i = 0; i < nb; ++i) {
-            const PrimPair pp = load_prim(pl, ps, b0 + kPrimLane * i);
-#pragma unroll 1
-            for (int j = 0; j < nk; ++j) body(pp, load_prim(pl, ps, k0 + kPrimLane * j));
-        }
+        for (int j = 0; j < nk; ++j) body(pp, load_prim(pl, ps, k0 + kPrimLane * j));
     }
-}
-
-// Classes that prefetch primitive records (high angular momentum, large
-// accumulator sets).
-template <class C>
-constexpr bool prim_prefetch() {
-    return C::L >= 5 && C::NACC >= 96;
 }
 
 // A shell pair record, read field by field through a global pointer.
@@ -352,7 +322,7 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
     double acc[C::NACC];
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    prim_loop<prim_prefetch<C>()>(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
+    prim_loop(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
               [&](const PrimPair& pp, const PrimPair& qq) {
                   VrrCoef<double> kd;
                   double T, pref;
@@ -382,7 +352,7 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
         double acc[C::GMAX];
 #pragma unroll
         for (int i = 0; i < C::GN[G]; ++i) acc[i] = 0.0;
-        prim_loop<prim_prefetch<C>()>(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
+        prim_loop(m, P.prim_off, P.nprim, Q.prim_off, Q.nprim,
                   [&](const PrimPair& pp, const PrimPair& qq) {
                       VrrCoef<double> kd;
                       double T, pref;
