@@ -73,7 +73,8 @@ template <int LA, int LB, int LC, int LD>
 struct DigShape {
     static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     static constexpr int NF = NA * NB * NC * ND, NAB = NA * NB, NCD = NC * ND;
-    static constexpr int QB = dig_qb(LA, LB, LC, LD, NF), QBP = QB + 1;
+    static constexpr int QB = dig_qb_c(LA, LB, LC, LD, NF), QBP = QB + 1;       // pass C
+    static constexpr int QB_D = dig_qb_d(LA, LB, LC, LD, NF), QBP_D = QB_D + 1;  // pass D
     static constexpr int WAVES_C = dig_waves_c(LA, LB, LC, LD), WAVES_D = 3;
     // accumulator tiles (16 output rows each) per update
     static constexpr int MJ = (NAB + 15) / 16;          // J_ab rows (i, j)
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(DigShape<LA
 void k_digest_d(DigestArgs a) {
     using S = DigShape<LA, LB, LC, LD>;
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NCD = S::NCD;
-    constexpr int QB = S::QB, QBP = S::QBP;
+    constexpr int QB = S::QB_D, QBP = S::QBP_D;
     constexpr int M5 = S::M5, M6 = S::M6, NACC = S::NACC_D;
     __shared__ double sT[NF * QBP];
     __shared__ int sV[QB];
