@@ -63,15 +63,15 @@ __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 // Quartets a digestion workgroup stages in LDS per chunk for class
 // (la lb | lc ld) with nf Cartesian functions per quartet, in pass C
 // (dig_qb_c) and pass D (dig_qb_d): a multiple of the MFMA k-depth 4 and at
-// most ~29 KB of LDS (52 KB for (dd|dd)); chosen by timing each class on
-// the 312-AO workload at 8, 16 and 32.
+// most ~47 KB of LDS (52 KB for (dd|dd)); chosen by timing each class on
+// the 312-AO workload at 4 to 32.
 __host__ __device__ constexpr int dig_qb_default(int nf) {
     return nf <= 27 ? 16 : (nf <= 90 ? 32 : (nf <= 170 ? 16 : (nf <= 324 ? 8 : 4)));
 }
 __host__ __device__ constexpr int dig_qb_c(int la, int lb, int lc, int ld, int nf) {
     const int t = la * 1000 + lb * 100 + lc * 10 + ld;
-    return t == 1110 ? 8
-           : (t == 2011 || t == 1111) ? 16
+    return (t == 1110 || t == 2221) ? 8
+           : (t == 2011 || t == 1111 || t == 2211) ? 16
            : (t == 1000 || t == 2000 || t == 2120) ? 32
            : dig_qb_default(nf);
 }
