@@ -239,8 +239,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
-                                   "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: sharding a build over GPUs (by quartets, then one "
+                                   "all-reduce of J and K) is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
