@@ -314,23 +314,33 @@ def test_batch_mixed_precision(dev):
         assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8)
 
 
-def test_batch_workload_64_molecules(dev):
+def test_batch_workload_64_molecules(dev, capsys):
     """The 64-molecule uneven workload in one batched build: every molecule
-    equals its own build; the six smallest against the oracle."""
+    equals its own build; the six smallest against the oracle.  Takes about
+    three minutes (mostly the 64 basis set-ups), so it reports progress on
+    the terminal even when output is captured."""
     import torch
+
+    def note(msg):
+        with capsys.disabled():
+            print(f"[batch-64] {msg}", flush=True)
+
     ws = synth.config3()
-    print("64-molecule workload generated", flush=True)
+    note("64-molecule workload generated")
     bases = [w.basis for w in ws]
     Ds = [w.D for w in ws]
-    hs = [jk.JKBasis(b) for b in bases]
-    print("64 handles created", flush=True)
+    hs = []
+    for i, b in enumerate(bases):
+        hs.append(jk.JKBasis(b))
+        if i % 8 == 7:
+            note(f"{i + 1} handles created")
     try:
         Dt = [torch.tensor(D, device=dev) for D in Ds]
         Jt, Kt = jk.jk_build_batch([h.h for h in hs], Dt)
         torch.cuda.synchronize()
         Jb = [J.cpu().numpy() for J in Jt]
         Kb = [K.cpu().numpy() for K in Kt]
-        print("batched build done", flush=True)
+        note("batched build done")
         for i in range(len(ws)):
             Js, Ks = hs[i].build(Dt[i])
             torch.cuda.synchronize()
@@ -338,11 +348,12 @@ def test_batch_workload_64_molecules(dev):
     finally:
         for h in hs:
             h.close()
-    print("each molecule equals its own build", flush=True)
+    note("each molecule equals its own build")
     order = np.argsort([b.nbf() for b in bases])
     for i in order[:6]:
         Jr, Kr = oracle.jk(bases[i], Ds[i], 1e-12)
         assert maxabs(Jb[i], Jr) <= TOL and maxabs(Kb[i], Kr) <= TOL, i
+        note(f"molecule {i} ({bases[i].nbf()} AO) matches the oracle")
 
 
 # ------------------------------------------------------------ HIP graphs ----
