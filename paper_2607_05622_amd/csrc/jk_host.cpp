@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "jk.h"
@@ -334,8 +335,45 @@ int compute_schwarz(jk_basis_s* h) {
     return JK_OK;
 }
 
+// Runs body(i) for i in [0, n) on up to hardware_concurrency() host threads
+// (at most 16), in contiguous chunks handed out dynamically.
+template <class Body>
+void parallel_for(long long n, Body body) {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const long long nt = std::min<long long>(hw, n);
+    if (nt <= 1) {
+        for (long long i = 0; i < n; ++i) body(i);
+        return;
+    }
+    const long long chunk = std::max<long long>(1, n / (nt * 8));
+    std::atomic<long long> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const long long i0 = next.fetch_add(chunk);
+            if (i0 >= n) return;
+            const long long i1 = std::min(n, i0 + chunk);
+            for (long long i = i0; i < i1; ++i) body(i);
+        }
+    };
+    std::vector<std::thread> ts;
+    for (long long t = 1; t < nt; ++t) ts.emplace_back(worker);
+    worker();
+    for (auto& t : ts) t.join();
+}
+
+// One bra pair's share of a class list: its kept ket pairs per tier (ket
+// index order) and the digestion parts of each of its two blocks per pass
+// (start positions within the block).
+struct BraLists {
+    std::vector<int> keep[2];
+    std::vector<int> parts[2][2];   // [tier][pass]
+    double primq[2] = {0, 0};
+};
+
 // Build the class-bucketed quartet lists kept by Q_ab Q_cd >= tol.  Within a
-// class: bra pair outer, ket pairs in index order.
+// class: bra pair outer, ket pairs in index order.  The bra pairs of a class
+// are independent: their keep lists, (d, c) orders and digestion parts are
+// made on host threads, then written at offsets from a prefix sum.
 int build_lists(jk_basis_s* h, double tol, double bound) {
     ClassList fresh[kNumClass];
     for (int X = 0; X < kNumPairClass; ++X) {
@@ -349,12 +387,16 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
             // ket pairs sorted by Q, descending, to stop early
             std::vector<int> ks(ket);
             std::sort(ks.begin(), ks.end(), [&](int u, int v) { return h->pairs[u].q > h->pairs[v].q; });
-            std::vector<int2> tier[2];
-            std::vector<int> keep;
-            double primq[2] = {0, 0};
-            for (int b : bra) {
+            const int cap = std::max(4, tune_of(cls).seg_max);
+            const bool pack = kClassCost[cls].nfunc <= 18;
+            const size_t nbra = bra.size();
+            std::vector<BraLists> bl(nbra);
+            // phase 1: per bra pair, its kept kets per tier and the parts of its blocks
+            parallel_for(static_cast<long long>(nbra), [&](long long bi) {
+                const int b = bra[bi];
+                BraLists& B = bl[bi];
                 const double qb = h->pairs[b].q;
-                keep.clear();
+                std::vector<int> keep;
                 for (int k : ks) {
                     if (qb * h->pairs[k].q < tol) break;
                     if (X == Y && k > b) continue;
@@ -363,44 +405,27 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                 std::sort(keep.begin(), keep.end());
                 for (int k : keep) {
                     const int t = fp32_ok && qb * h->pairs[k].q < bound ? 1 : 0;
-                    tier[t].push_back(make_int2(b, k));
-                    primq[t] += static_cast<double>(h->pairs[b].nprim) * h->pairs[k].nprim;
+                    B.keep[t].push_back(k);
+                    B.primq[t] += static_cast<double>(h->pairs[b].nprim) * h->pairs[k].nprim;
                 }
-            }
-            std::vector<int2> out(tier[0]);
-            out.insert(out.end(), tier[1].begin(), tier[1].end());
-            ClassList& F = fresh[cls];
-            F.count = static_cast<long long>(out.size());
-            F.n64 = static_cast<long long>(tier[0].size());
-            F.prim_quartets[0] = primq[0];
-            F.prim_quartets[1] = primq[1];
-            // blocks (one bra pair, one tier), their (d, c) orders and the
-            // ket shells and functions the digestion reads per position
-            std::vector<int> pos(out.size()), idx, parts[2];
-            std::vector<int2> kin(out.size()), kind(out.size());
-            const int cap = std::max(4, tune_of(cls).seg_max);
-            const bool pack = kClassCost[cls].nfunc <= 18;
-            for (size_t q = 0; q < out.size(); ++q) {
-                const PairInfo& Q = h->pairs[out[q].y];
-                kin[q] = make_int2(Q.sa | (Q.sb << 16), Q.fa | (Q.fb << 16));
-            }
-            for (int t = 0; t < 2; ++t) {
-                const size_t lo = t ? tier[0].size() : 0, hi = t ? out.size() : tier[0].size();
-                for (size_t q = lo; q < hi;) {
-                    size_t e = q + 1;
-                    while (e < hi && out[e].x == out[q].x) ++e;
-                    F.blocks.push_back(make_int2(static_cast<int>(q), static_cast<int>(e - q)));
-                    F.block_bra.push_back(out[q].x);
-                    idx.resize(e - q);
-                    for (size_t i = 0; i < idx.size(); ++i) idx[i] = static_cast<int>(i);
+                std::vector<int> idx, sv[2];
+                for (int t = 0; t < 2; ++t) {
+                    const std::vector<int>& kp = B.keep[t];
+                    const size_t n = kp.size();
+                    if (n == 0) continue;
+                    // ket shell c (pass C, list order) and d (pass D, (d, c) order) per position
+                    idx.resize(n);
+                    for (size_t i = 0; i < n; ++i) idx[i] = static_cast<int>(i);
                     std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
-                        const PairInfo& U = h->pairs[out[q + u].y];
-                        const PairInfo& V = h->pairs[out[q + v].y];
+                        const PairInfo& U = h->pairs[kp[u]];
+                        const PairInfo& V = h->pairs[kp[v]];
                         return U.sb != V.sb ? U.sb < V.sb : U.sa < V.sa;
                     });
-                    for (size_t p = 0; p < idx.size(); ++p) {
-                        kind[q + p] = kin[q + idx[p]];
-                        pos[q + idx[p]] = static_cast<int>(p);
+                    sv[0].resize(n);
+                    sv[1].resize(n);
+                    for (size_t i = 0; i < n; ++i) {
+                        sv[0][i] = h->pairs[kp[i]].sa;
+                        sv[1][i] = h->pairs[kp[idx[i]]].sb;
                     }
                     // parts: runs of equal c (pass C) or d (pass D), a run
                     // longer than cap cut into pieces of cap.  Classes of at
@@ -408,34 +433,105 @@ int build_lists(jk_basis_s* h, double tol, double bound) {
                     // runs into one part up to cap positions: their runs are
                     // short and a workgroup's set-up outweighs its work.
                     for (int ps = 0; ps < 2; ++ps) {
-                        const std::vector<int2>& kv = ps ? kind : kin;
-                        const int shift = ps ? 16 : 0;
+                        const std::vector<int>& kv = sv[ps];
+                        std::vector<int>& out = B.parts[t][ps];
                         const size_t ucap = static_cast<size_t>(cap), none = ~size_t(0);
-                        F.part_off[ps].push_back(static_cast<int>(parts[ps].size()));
                         size_t open = none;   // first position of the part being filled
-                        for (size_t p = q; p < e;) {
+                        for (size_t p = 0; p < n;) {
                             size_t r = p + 1;
-                            while (r < e && ((kv[r].x >> shift) & 0xffff) == ((kv[p].x >> shift) & 0xffff)) ++r;
+                            while (r < n && kv[r] == kv[p]) ++r;
                             if (r - p > ucap) {
-                                if (open != none) parts[ps].push_back(static_cast<int>(open - q));
+                                if (open != none) out.push_back(static_cast<int>(open));
                                 open = none;
-                                for (size_t c = p; c < r; c += ucap) parts[ps].push_back(static_cast<int>(c - q));
+                                for (size_t c = p; c < r; c += ucap) out.push_back(static_cast<int>(c));
                             } else {
                                 if (open != none && (!pack || r - open > ucap)) {
-                                    parts[ps].push_back(static_cast<int>(open - q));
+                                    out.push_back(static_cast<int>(open));
                                     open = none;
                                 }
                                 if (open == none) open = p;
                             }
                             p = r;
                         }
-                        if (open != none) parts[ps].push_back(static_cast<int>(open - q));
+                        if (open != none) out.push_back(static_cast<int>(open));
                     }
-                    q = e;
+                }
+            });
+            // phase 2: offsets of every bra pair's blocks (FP64 tier, then FP32 tier)
+            ClassList& F = fresh[cls];
+            std::vector<long long> qoff[2];
+            std::vector<int> boff[2];
+            long long nq[2] = {0, 0};
+            for (int t = 0; t < 2; ++t) {
+                qoff[t].resize(nbra);
+                boff[t].resize(nbra);
+                for (size_t bi = 0; bi < nbra; ++bi) {
+                    qoff[t][bi] = nq[t];
+                    nq[t] += static_cast<long long>(bl[bi].keep[t].size());
+                }
+                F.prim_quartets[t] = 0.0;
+                for (size_t bi = 0; bi < nbra; ++bi) F.prim_quartets[t] += bl[bi].primq[t];
+            }
+            const long long total = nq[0] + nq[1];
+            F.count = total;
+            F.n64 = nq[0];
+            for (int t = 0; t < 2; ++t) {
+                for (size_t bi = 0; bi < nbra; ++bi) {
+                    if (bl[bi].keep[t].empty()) continue;
+                    const long long q0 = (t ? nq[0] : 0) + qoff[t][bi];
+                    F.blocks.push_back(make_int2(static_cast<int>(q0), static_cast<int>(bl[bi].keep[t].size())));
+                    F.block_bra.push_back(bra[bi]);
+                    boff[t][bi] = static_cast<int>(F.blocks.size()) - 1;
                 }
                 if (t == 0) F.nblk64 = static_cast<int>(F.blocks.size());
             }
-            for (int ps = 0; ps < 2; ++ps) F.part_off[ps].push_back(static_cast<int>(parts[ps].size()));
+            // part_off[ps][k] is the first part of block k; fill it from the part counts
+            const int nblk = static_cast<int>(F.blocks.size());
+            std::vector<int> parts[2];
+            for (int ps = 0; ps < 2; ++ps) {
+                F.part_off[ps].assign(nblk + 1, 0);
+                for (int t = 0; t < 2; ++t)
+                    for (size_t bi = 0; bi < nbra; ++bi)
+                        if (!bl[bi].keep[t].empty())
+                            F.part_off[ps][boff[t][bi] + 1] = static_cast<int>(bl[bi].parts[t][ps].size());
+                for (int k = 0; k < nblk; ++k) F.part_off[ps][k + 1] += F.part_off[ps][k];
+                parts[ps].resize(F.part_off[ps][nblk]);
+            }
+            // phase 3: every bra pair writes its quartets, ket records, (d, c)
+            // positions and parts at its offsets
+            std::vector<int2> out(total), kin(total), kind(total);
+            std::vector<int> pos(total);
+            parallel_for(static_cast<long long>(nbra), [&](long long bi) {
+                const int b = bra[bi];
+                std::vector<int> idx;
+                for (int t = 0; t < 2; ++t) {
+                    const std::vector<int>& kp = bl[bi].keep[t];
+                    const size_t n = kp.size();
+                    if (n == 0) continue;
+                    const long long q0 = (t ? nq[0] : 0) + qoff[t][bi];
+                    for (size_t i = 0; i < n; ++i) {
+                        const PairInfo& Q = h->pairs[kp[i]];
+                        out[q0 + i] = make_int2(b, kp[i]);
+                        kin[q0 + i] = make_int2(Q.sa | (Q.sb << 16), Q.fa | (Q.fb << 16));
+                    }
+                    idx.resize(n);
+                    for (size_t i = 0; i < n; ++i) idx[i] = static_cast<int>(i);
+                    std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
+                        const PairInfo& U = h->pairs[kp[u]];
+                        const PairInfo& V = h->pairs[kp[v]];
+                        return U.sb != V.sb ? U.sb < V.sb : U.sa < V.sa;
+                    });
+                    for (size_t p = 0; p < n; ++p) {
+                        kind[q0 + p] = kin[q0 + idx[p]];
+                        pos[q0 + idx[p]] = static_cast<int>(p);
+                    }
+                    const int k = boff[t][bi];
+                    for (int ps = 0; ps < 2; ++ps)
+                        std::copy(bl[bi].parts[t][ps].begin(), bl[bi].parts[t][ps].end(),
+                                  parts[ps].begin() + F.part_off[ps][k]);
+                }
+            });
+            std::vector<BraLists>().swap(bl);
             if (!out.empty()) {
                 int rc = upload(&F.dev, out);
                 if (!rc) rc = upload(&F.dev_pos, pos);
@@ -1121,8 +1217,11 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     return e;
 }
 
+// Outputs the build does not produce are never touched: their pointers are
+// dropped here (the caller may pass any value for them).
 hipError_t mol_post(const jk_basis_s* h, int nd, const MolDesc& md, double* J, double* K, hipStream_t s) {
-    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, md.ndp, J, K, s);
+    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, md.ndp, md.J ? J : nullptr,
+                           md.K ? K : nullptr, s);
 }
 
 int check_opts(const char* who, const jk_build_opts* o) {

@@ -42,7 +42,9 @@ __global__ void k_sph2cart(const double* __restrict__ D, int nd, int nf, const C
 
 // J[x][m][n] = sum T[i][m] (Jc[i][j][x] + Jc[j][i][x]) T[j][n] and
 // K[x][m][n] = sum T[i][m] (Kc[i][j][x] + KTc[j][i][x]) T[j][n], accumulators
-// density-innermost with stride ndp.
+// density-innermost with stride ndp.  A matrix is written only when both its
+// accumulator and its output are given (a build without J or K has no
+// accumulator for it, whatever output pointer the caller passed).
 __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restrict__ Kc,
                            const double* __restrict__ KTc, int nd, int nf, const UserMap* __restrict__ umap,
                            int nc, int ndp, double* __restrict__ J, double* __restrict__ K) {
@@ -50,6 +52,7 @@ __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restri
     if (t >= static_cast<long long>(nf) * nf) return;
     const int m = static_cast<int>(t / nf), n = static_cast<int>(t - static_cast<long long>(m) * nf);
     const UserMap um = umap[m], un = umap[n];
+    const bool doj = Jc && J, dok = Kc && KTc && K;
     for (int x = 0; x < nd; ++x) {
         double sj = 0.0, sk = 0.0;
         for (int u = 0; u < um.n; ++u)
@@ -57,11 +60,11 @@ __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restri
                 const double c = um.c[u] * un.c[v];
                 const long long ij = (static_cast<long long>(um.idx[u]) * nc + un.idx[v]) * ndp + x;
                 const long long ji = (static_cast<long long>(un.idx[v]) * nc + um.idx[u]) * ndp + x;
-                if (J) sj = fma(c, Jc[ij] + Jc[ji], sj);
-                if (K) sk = fma(c, Kc[ij] + KTc[ji], sk);
+                if (doj) sj = fma(c, Jc[ij] + Jc[ji], sj);
+                if (dok) sk = fma(c, Kc[ij] + KTc[ji], sk);
             }
-        if (J) J[static_cast<long long>(x) * nf * nf + t] = sj;
-        if (K) K[static_cast<long long>(x) * nf * nf + t] = sk;
+        if (doj) J[static_cast<long long>(x) * nf * nf + t] = sj;
+        if (dok) K[static_cast<long long>(x) * nf * nf + t] = sk;
     }
 }
 

@@ -200,13 +200,15 @@ def random_shell(rng: np.random.Generator, l: int, nprim: int = NPRIM):
 
 
 def make_basis(rng: np.random.Generator, n_atoms: int, n_heavy: int,
-               heavy=HEAVY_SPD, light=LIGHT, spherical: int = 1) -> Basis:
+               heavy=HEAVY_SPD, light=LIGHT, spherical: int = 1, nprims=(NPRIM,)) -> Basis:
+    """Shell k of the molecule (in order) gets nprims[k % len(nprims)]
+    primitives."""
     xyz = random_geometry(rng, n_atoms)
     charges = np.array([8.0] * n_heavy + [1.0] * (n_atoms - n_heavy))
     sa, sl, sn, ex, co = [], [], [], [], []
     for ia in range(n_atoms):
         for l in (heavy if ia < n_heavy else light):
-            e, c = random_shell(rng, l)
+            e, c = random_shell(rng, l, int(nprims[len(sl) % len(nprims)]))
             sa.append(ia)
             sl.append(l)
             sn.append(len(e))
@@ -517,10 +519,11 @@ def request_densities(orb: Orbitals, nd: int, seed: int) -> np.ndarray:
 
 
 def random_basis(seed: int, n_atoms: int, n_heavy: int, spherical: int = 1,
-                 heavy=HEAVY_SPD, light=LIGHT) -> Basis:
-    """A small seeded basis for tests (same recipe as the workloads)."""
+                 heavy=HEAVY_SPD, light=LIGHT, nprims=(NPRIM,)) -> Basis:
+    """A small seeded basis for tests (same recipe as the workloads; nprims
+    cycles the contraction lengths over the shells)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return make_basis(rng, n_atoms, n_heavy, heavy=heavy, light=light, spherical=spherical)
+    return make_basis(rng, n_atoms, n_heavy, heavy=heavy, light=light, spherical=spherical, nprims=nprims)
 
 
 def random_densities(seed: int, nd: int, n: int, scale: float = 0.1,

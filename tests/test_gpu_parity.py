@@ -1,12 +1,16 @@
 """GPU parity: the HIP path through the C-ABI against the CPU oracle.
 
 FP64 path bar: max |dJ|, |dK| <= 1e-10 per element (absolute), the bar the
-build states for its FP64 path.  Integrals are checked class by class; whole
-builds on small bases span several tiles and ragged density counts; the
-312-AO workload is checked at full size in the benchmark's launch
-configuration on sampled shell-pair blocks the oracle computes one by one.
+build states for its FP64 path.  Mixed path bar: per density
+||dJ||_F/||J||_F and ||dK||_F/||K||_F <= 1e-8 against the FP64 oracle.
+Integrals are checked class by class; whole builds on small bases span
+several tiles and ragged density counts; the 312-AO workload is checked at
+full size, every element, against the whole oracle build; the 620-AO
+workload on sampled shell-pair blocks of every pair class the oracle
+computes one by one.
 """
 import itertools
+import time
 
 import numpy as np
 import pytest
@@ -120,6 +124,33 @@ def test_want_flags_and_zero_density(dev):
     assert np.all(J == 0) and np.all(K == 0)
 
 
+def test_unwanted_output_pointer_is_never_touched(dev):
+    """want_j = 0 (or want_k = 0) with a non-NULL output pointer, through the
+    raw C-ABI: the unwanted buffer keeps its sentinel values and the wanted
+    matrix matches the oracle."""
+    import ctypes
+    import torch
+    b = synth.random_basis(304, 3, 2)
+    D = synth.random_densities(5, 3, b.nbf())
+    Jr, Kr = oracle.jk(b, D, 1e-12)
+    h = jk.JKBasis(b)
+    lib = jk.load()
+    Dt = torch.tensor(D, device=dev)
+    for want_j, want_k in ((0, 1), (1, 0)):
+        o = jk.jk_default_opts(want_j=want_j, want_k=want_k)
+        J = torch.full_like(Dt, 12345.0)
+        K = torch.full_like(Dt, -6789.0)
+        rc = lib.jk_build(h.h, Dt.shape[0], Dt.data_ptr(), J.data_ptr(), K.data_ptr(), ctypes.byref(o))
+        assert rc == jk.JK_OK, jk.jk_last_error()
+        torch.cuda.synchronize()
+        J, K = J.cpu().numpy(), K.cpu().numpy()
+        if want_j:
+            assert maxabs(J, Jr) <= TOL and np.all(K == -6789.0)
+        else:
+            assert maxabs(K, Kr) <= TOL and np.all(J == 12345.0)
+    h.close()
+
+
 def test_structure_of_gpu_results(dev):
     b = synth.random_basis(404, 4, 2)
     D = synth.random_densities(4, 2, b.nbf())
@@ -178,24 +209,26 @@ def test_invalid_build_arguments(dev):
     b.close()
 
 
-def test_medium_workload_sampled_blocks(dev):
-    """312 AO, 16 Laplace pseudo-densities: full-size build, checked on
-    sampled shell-pair blocks (every pair class, diagonal and off-diagonal)."""
+@pytest.fixture(scope="module")
+def medium_ref():
+    """The 312-AO workload (16 Laplace pseudo-densities) and the oracle's
+    whole screened build of it (about two minutes on 16 host threads)."""
     w = synth.config1()
+    t0 = time.perf_counter()
+    Jr, Kr = oracle.jk(w.basis, w.D, 1e-12)
+    print(f"medium oracle: {time.perf_counter() - t0:.1f} s on {oracle.threads()} threads", flush=True)
+    return w, Jr, Kr
+
+
+def test_medium_workload_full_fp64(dev, medium_ref):
+    """312 AO, 16 non-symmetric densities, the benchmark's launch
+    configuration: every element of J and K against the oracle."""
+    w, Jr, Kr = medium_ref
     J, K = gpu_jk(w.basis, w.D, dev)
-    l = w.basis.shell_l
-    rng = np.random.default_rng(1)
-    pairs = []
-    for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (0, 2)]:
-        A = [int(s) for s in np.nonzero(l == la)[0]]
-        B = [int(s) for s in np.nonzero(l == lb)[0]]
-        pairs.append((A[int(rng.integers(len(A)))], B[int(rng.integers(len(B)))]))
-    fo = w.basis.func_offsets()
-    for (a, c), (Jb, Kb) in zip(pairs, oracle.jk_blocks(w.basis, w.D, pairs, 1e-12)):
-        assert maxabs(J[:, fo[a]:fo[a + 1], fo[c]:fo[c + 1]], Jb) <= TOL, (a, c)
-        assert maxabs(K[:, fo[a]:fo[a + 1], fo[c]:fo[c + 1]], Kb) <= TOL, (a, c)
-    # properties that hold at any size
-    assert maxabs(J, J.transpose(0, 2, 1)) <= 1e-12 * np.max(np.abs(J))
+    ej, ek = maxabs(J, Jr), maxabs(K, Kr)
+    print(f"medium fp64: max|dJ| {ej:.2e} max|dK| {ek:.2e} (max|J| {np.max(np.abs(Jr)):.2f}, "
+          f"max|K| {np.max(np.abs(Kr)):.2f})")
+    assert ej <= TOL and ek <= TOL
 
 
 # ------------------------------------------------------------ mixed tier ----
@@ -203,6 +236,25 @@ def test_medium_workload_sampled_blocks(dev):
 def rel_frob(a, b):
     """Per-density ||a - b||_F / ||b||_F."""
     return np.sqrt(np.sum((a - b) ** 2, axis=(1, 2)) / np.maximum(np.sum(b ** 2, axis=(1, 2)), 1e-300))
+
+
+def fp32_tier_count(b, tol, bound):
+    """Canonical shell quartets kept by Q_ab Q_cd >= tol, and of those the
+    ones with Q_ab Q_cd < bound and la + lb + lc + ld <= 4, from the oracle's
+    Schwarz factors."""
+    Q = oracle.schwarz(b)
+    l = np.asarray(b.shell_l)
+    ns = len(l)
+    pa, pb = np.tril_indices(ns)
+    q = Q[pa, pb]
+    lp = l[pa] + l[pb]
+    n_all = n32 = 0
+    for i in range(len(q)):
+        qq = q[i] * q[:i + 1]
+        keep = qq >= tol
+        n_all += int(keep.sum())
+        n32 += int((keep & (qq < bound) & (lp[i] + lp[:i + 1] <= 4)).sum())
+    return n_all, n32
 
 
 def test_mixed_precision_against_oracle(dev):
@@ -217,7 +269,14 @@ def test_mixed_precision_against_oracle(dev):
     st = h.stats()
     h.close()
     J, K = J.cpu().numpy(), K.cpu().numpy()
-    assert st["quartets_fp32"] > 0.1 * st["quartets"]        # the FP32 tier is exercised
+    # the FP32 tier holds exactly the Schwarz-kept quartets with Q_ab Q_cd
+    # below the bound and total angular momentum <= 4, counted here from the
+    # oracle's Schwarz factors; on this basis that is about a quarter
+    n_all, n32 = fp32_tier_count(b, 1e-12, 1e-6)
+    print(f"mixed: {st['quartets_fp32']:.0f} of {st['quartets']:.0f} quartets in FP32 "
+          f"(oracle count {n32} of {n_all})")
+    assert st["quartets"] == n_all and st["quartets_fp32"] == n32
+    assert n32 > 0.2 * n_all                                   # the FP32 tier is exercised
     assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8)
     print("mixed: max rel-Frobenius J %.2e K %.2e, max-abs J %.2e K %.2e" % (
         rel_frob(J, Jr).max(), rel_frob(K, Kr).max(), maxabs(J, Jr), maxabs(K, Kr)))
@@ -231,50 +290,103 @@ def test_mixed_bound_zero_is_fp64(dev):
     assert maxabs(J1, J2) <= 1e-13 and maxabs(K1, K2) <= 1e-13
 
 
-def test_mixed_medium_workload(dev):
-    """312 AO, 16 densities: mixed against the GPU's own FP64 build (whole
-    matrices) and against the oracle on sampled blocks."""
-    w = synth.config1()
-    J64, K64 = gpu_jk(w.basis, w.D, dev)
+def test_medium_workload_full_mixed(dev, medium_ref):
+    """312 AO, 16 densities, mixed precision: per density relative
+    Frobenius error of J and K against the whole oracle build."""
+    w, Jr, Kr = medium_ref
     Jm, Km = gpu_jk(w.basis, w.D, dev, precision=jk.JK_MIXED)
-    assert np.all(rel_frob(Jm, J64) <= 1e-8) and np.all(rel_frob(Km, K64) <= 1e-8)
-    fo = w.basis.func_offsets()
-    pairs = [(0, 0), (40, 7), (143, 60), (100, 130)]
-    for (a, c), (Jb, Kb) in zip(pairs, oracle.jk_blocks(w.basis, w.D, pairs, 1e-12)):
-        sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
-        scale_j = np.max(np.abs(J64), axis=(1, 2))[:, None, None]
-        scale_k = np.max(np.abs(K64), axis=(1, 2))[:, None, None]
-        assert np.all(np.abs(Jm[sl] - Jb) <= 1e-8 * scale_j)
-        assert np.all(np.abs(Km[sl] - Kb) <= 1e-8 * scale_k)
+    ej, ek = rel_frob(Jm, Jr), rel_frob(Km, Kr)
+    print(f"medium mixed vs oracle per density: max rel-Frobenius J {ej.max():.2e} K {ek.max():.2e}, "
+          f"max-abs J {maxabs(Jm, Jr):.2e} K {maxabs(Km, Kr):.2e}")
+    assert np.all(ej <= 1e-8) and np.all(ek <= 1e-8)
 
 
-def test_large_workload_fp64_and_mixed(dev):
-    """620 AO, 40 non-symmetric densities (the memory-ceiling molecule):
-    FP64 against the oracle on sampled shell-pair blocks of every pair
-    class, mixed against FP64 per density over whole matrices and against
-    the oracle on the same blocks."""
-    w = synth.config2()
-    print(f"large workload: {w.basis.nbf()} AO, {w.D.shape[0]} densities", flush=True)
-    J64, K64 = gpu_jk(w.basis, w.D, dev)
-    Jm, Km = gpu_jk(w.basis, w.D, dev, precision=jk.JK_MIXED)
-    l = w.basis.shell_l
-    rng = np.random.default_rng(2)
-    pairs = []
-    for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]:
+def sample_blocks(basis, seed, per_class=3,
+                  classes=((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (0, 2))):
+    """per_class shell-pair blocks (A, B) of every (l_A, l_B), drawn with a
+    seeded generator."""
+    l = basis.shell_l
+    rng = np.random.default_rng(seed)
+    out = []
+    for la, lb in classes:
         A = [int(s) for s in np.nonzero(l == la)[0]]
         B = [int(s) for s in np.nonzero(l == lb)[0]]
-        pairs.append((A[int(rng.integers(len(A)))], B[int(rng.integers(len(B)))]))
-    fo = w.basis.func_offsets()
-    scale_j = np.max(np.abs(J64), axis=(1, 2))[:, None, None]
-    scale_k = np.max(np.abs(K64), axis=(1, 2))[:, None, None]
-    for (a, c), (Jb, Kb) in zip(pairs, oracle.jk_blocks(w.basis, w.D, pairs, 1e-12)):
+        for _ in range(per_class):
+            out.append((A[int(rng.integers(len(A)))], B[int(rng.integers(len(B)))]))
+    return out
+
+
+def block_errors(J, K, basis, blocks, refs):
+    """Max-abs over the blocks, and per density the relative Frobenius
+    error restricted to the blocks."""
+    fo = basis.func_offsets()
+    ej = ek = 0.0
+    nd = J.shape[0]
+    dj2, dk2, rj2, rk2 = np.zeros(nd), np.zeros(nd), np.zeros(nd), np.zeros(nd)
+    for (a, c), (Jb, Kb) in zip(blocks, refs):
         sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
-        assert maxabs(J64[sl], Jb) <= TOL and maxabs(K64[sl], Kb) <= TOL, (a, c)
-        assert np.all(np.abs(Jm[sl] - Jb) <= 1e-8 * scale_j) and np.all(np.abs(Km[sl] - Kb) <= 1e-8 * scale_k)
-    ej, ek = rel_frob(Jm, J64), rel_frob(Km, K64)
-    print("large mixed vs fp64 per density: max rel-Frobenius J %.2e K %.2e" % (ej.max(), ek.max()))
-    assert np.all(ej <= 1e-8) and np.all(ek <= 1e-8)
+        ej = max(ej, maxabs(J[sl], Jb))
+        ek = max(ek, maxabs(K[sl], Kb))
+        dj2 += np.sum((J[sl] - Jb) ** 2, axis=(1, 2))
+        dk2 += np.sum((K[sl] - Kb) ** 2, axis=(1, 2))
+        rj2 += np.sum(Jb ** 2, axis=(1, 2))
+        rk2 += np.sum(Kb ** 2, axis=(1, 2))
+    return ej, ek, np.sqrt(dj2 / rj2), np.sqrt(dk2 / rk2)
+
+
+@pytest.fixture(scope="module")
+def large_run(dev):
+    """The 620-AO workload (40 densities): FP64 and mixed GPU builds in the
+    benchmark's launch configuration, and 21 oracle blocks, three of every
+    shell-pair class."""
+    w = synth.config2()
+    print(f"large workload: {w.basis.nbf()} AO, {w.D.shape[0]} densities", flush=True)
+    t0 = time.perf_counter()
+    J64, K64 = gpu_jk(w.basis, w.D, dev)
+    Jm, Km = gpu_jk(w.basis, w.D, dev, precision=jk.JK_MIXED)
+    print(f"large: two GPU builds with set-up {time.perf_counter() - t0:.1f} s", flush=True)
+    blocks = sample_blocks(w.basis, 2)
+    t0 = time.perf_counter()
+    refs = oracle.jk_blocks(w.basis, w.D, blocks, 1e-12)
+    print(f"large: {len(blocks)} oracle blocks {time.perf_counter() - t0:.1f} s", flush=True)
+    return w, J64, K64, Jm, Km, blocks, refs
+
+
+def test_large_workload_fp64_blocks(dev, large_run):
+    """620 AO, 40 non-symmetric densities (the memory-ceiling molecule), FP64:
+    three sampled shell-pair blocks of every pair class against the oracle,
+    element by element; J symmetric at any size."""
+    w, J64, K64, _, _, blocks, refs = large_run
+    ej, ek, _, _ = block_errors(J64, K64, w.basis, blocks, refs)
+    print(f"large fp64 on {len(blocks)} blocks: max|dJ| {ej:.2e} max|dK| {ek:.2e}")
+    assert ej <= TOL and ek <= TOL
     assert maxabs(J64, J64.transpose(0, 2, 1)) <= 1e-12 * np.max(np.abs(J64))
+
+
+def test_large_workload_mixed(dev, large_run):
+    """620 AO, 40 densities, mixed precision: against the oracle on the
+    sampled blocks (per density relative Frobenius over the blocks, and
+    max-abs), and against the GPU's FP64 build over whole matrices."""
+    w, J64, K64, Jm, Km, blocks, refs = large_run
+    ej, ek, fj, fk = block_errors(Jm, Km, w.basis, blocks, refs)
+    gj, gk = rel_frob(Jm, J64), rel_frob(Km, K64)
+    print(f"large mixed vs oracle on blocks: max-abs J {ej:.2e} K {ek:.2e}, per density rel-Frobenius "
+          f"J {fj.max():.2e} K {fk.max():.2e}; vs GPU FP64 whole matrices J {gj.max():.2e} K {gk.max():.2e}")
+    assert np.all(fj <= 1e-8) and np.all(fk <= 1e-8)
+    assert np.all(gj <= 1e-8) and np.all(gk <= 1e-8)
+
+
+def test_mixed_contraction_lengths(dev):
+    """Shells of 1, 2, 7 and 16 primitives in one basis (the interleaved
+    primitive-pair records pad each group of 64 pairs to its longest list),
+    FP64 and mixed, against the oracle."""
+    b = synth.random_basis(1700, 3, 1, nprims=(1, 2, 7, 16))
+    D = synth.random_densities(1701, 3, b.nbf())
+    Jr, Kr = oracle.jk(b, D, 1e-12)
+    J, K = gpu_jk(b, D, dev)
+    assert maxabs(J, Jr) <= TOL and maxabs(K, Kr) <= TOL
+    Jm, Km = gpu_jk(b, D, dev, precision=jk.JK_MIXED)
+    assert np.all(rel_frob(Jm, Jr) <= 1e-8) and np.all(rel_frob(Km, Kr) <= 1e-8)
 
 
 # ------------------------------------------------------- batched launch ----
@@ -316,9 +428,9 @@ def test_batch_mixed_precision(dev):
 
 def test_batch_workload_64_molecules(dev, capsys):
     """The 64-molecule uneven workload in one batched build: every molecule
-    equals its own build; the six smallest against the oracle.  Takes about
-    three minutes (mostly the 64 basis set-ups), so it reports progress on
-    the terminal even when output is captured."""
+    equals its own build; the eight smallest against the whole oracle build,
+    the four largest on sampled shell-pair blocks.  Reports progress on the
+    terminal even when output is captured."""
     import torch
 
     def note(msg):
@@ -350,10 +462,17 @@ def test_batch_workload_64_molecules(dev, capsys):
             h.close()
     note("each molecule equals its own build")
     order = np.argsort([b.nbf() for b in bases])
-    for i in order[:6]:
+    for i in order[:8]:
         Jr, Kr = oracle.jk(bases[i], Ds[i], 1e-12)
         assert maxabs(Jb[i], Jr) <= TOL and maxabs(Kb[i], Kr) <= TOL, i
         note(f"molecule {i} ({bases[i].nbf()} AO) matches the oracle")
+    for i in order[-4:]:
+        blocks = sample_blocks(bases[i], 30 + int(i), per_class=1)
+        refs = oracle.jk_blocks(bases[i], Ds[i], blocks, 1e-12)
+        ej, ek, _, _ = block_errors(Jb[i], Kb[i], bases[i], blocks, refs)
+        assert ej <= TOL and ek <= TOL, (i, ej, ek)
+        note(f"molecule {i} ({bases[i].nbf()} AO, {Ds[i].shape[0]} densities) matches the oracle "
+             f"on {len(blocks)} blocks")
 
 
 # ------------------------------------------------------------ HIP graphs ----

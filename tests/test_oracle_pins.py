@@ -407,3 +407,149 @@ def test_blocks_equal_full_build():
 def test_quartet_count_matches_workload_table():
     w = synth.config0()
     assert oracle.count_quartets(w.basis, w.D, 0.0) == 9316
+
+
+# ------------------------------------------------- screening quantities ----
+
+def _shell_slices(b, cart=True):
+    l = np.asarray(b.shell_l)
+    n = (l + 1) * (l + 2) // 2 if cart else b.shell_nfunc()
+    off = np.concatenate([[0], np.cumsum(n)])
+    return [slice(int(off[s]), int(off[s + 1])) for s in range(len(l))]
+
+
+@pytest.mark.parametrize("seed,atoms,heavy", [(41, 3, 2), (42, 4, 1)])
+def test_schwarz_equals_full_tensor_diagonal(seed, atoms, heavy):
+    """Q_ab = sqrt(max over m in a, n in b of (mn|mn)), read off the full
+    Cartesian ERI tensor (a Cartesian basis, so the tensor's functions are
+    the ones the factors are defined over)."""
+    b = synth.random_basis(seed, atoms, heavy, spherical=0)
+    G = oracle.eri_full(b)
+    n = G.shape[0]
+    diag = np.einsum("mnmn->mn", G)
+    sl = _shell_slices(b)
+    ns = len(sl)
+    ref = np.array([[math.sqrt(diag[sl[a], sl[c]].max()) for c in range(ns)] for a in range(ns)])
+    Q = oracle.schwarz(b)
+    assert n == sum(s.stop - s.start for s in sl)
+    assert np.max(np.abs(Q - ref) / ref) <= 1e-14
+    assert np.all(Q == Q.T)
+
+
+def _pair_dmax(b, D):
+    """Per shell pair, max |D_cart| over the batch and both orientations,
+    with D_cart = T D T^T from the input generator's own T."""
+    T = synth.cart_to_basis_matrix(b)
+    Dc = T[None] @ np.asarray(D).reshape(-1, *np.shape(D)[-2:]) @ T.T[None]
+    A = np.max(np.abs(Dc), axis=0)
+    A = np.maximum(A, A.T)
+    sl = _shell_slices(b)
+    return np.array([[A[sa, sb].max() for sb in sl] for sa in sl]), Dc
+
+
+def _keep(Q, M, a, b_, c, d, tol):
+    qq = Q[a, b_] * Q[c, d]
+    if qq < tol:
+        return False
+    m = max(M[a, b_], M[c, d], M[a, c], M[a, d], M[b_, c], M[b_, d])
+    return qq * m >= tol
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-12, 1e-7, 1e-4])
+def test_quartet_count_brute_force(tol):
+    """The oracle's count of kept canonical quartets equals a direct
+    enumeration of a >= b, c >= d, (ab) >= (cd) with the screening rule
+    applied to Schwarz factors read off the full tensor and density maxima
+    from the input generator's basis change."""
+    for seed, atoms, heavy in [(43, 3, 2), (44, 5, 2)]:
+        b = synth.random_basis(seed, atoms, heavy, spherical=0)
+        D = synth.random_densities(seed, 3, b.nbf())
+        G = oracle.eri_full(b)
+        diag = np.einsum("mnmn->mn", G)
+        sl = _shell_slices(b)
+        ns = len(sl)
+        Q = np.array([[math.sqrt(diag[sl[a], sl[c]].max()) for c in range(ns)] for a in range(ns)])
+        M, _ = _pair_dmax(b, D)
+        pairs = [(a, bb) for a in range(ns) for bb in range(a + 1)]
+        n = 0
+        for i, (a, bb) in enumerate(pairs):
+            for c, d in pairs[:i + 1]:
+                n += _keep(Q, M, a, bb, c, d, tol)
+        assert oracle.count_quartets(b, D, tol) == n, (seed, tol)
+
+
+def _dropped_bounds(b, D, blocks, tol):
+    """Per element of each requested block (A, B), a bound on what the
+    screen drops from J and K (user basis): every dropped (ij|kl) obeys
+    |(ij|kl)| <= Q_ab Q_cd (Schwarz), so a dropped quartet moves J_ij by at
+    most Q_AB Q_CD sum_{k in C, l in D} |D_kl|, and K_ij likewise through
+    the quartet (A C | B D); the spherical transform multiplies by |T|."""
+    Q = oracle.schwarz(b)
+    M, Dc = _pair_dmax(b, D)
+    T = np.abs(synth.cart_to_basis_matrix(b))
+    sl, slf = _shell_slices(b), _shell_slices(b, cart=False)
+    ns = len(sl)
+    absD = np.abs(Dc)
+    blk = np.array([[absD[:, sl[c], sl[d]].sum(axis=(1, 2)) for d in range(ns)] for c in range(ns)])  # [C][D][x]
+    out = []
+    for A, B in blocks:
+        bj = np.zeros(Dc.shape[0])
+        bk = np.zeros(Dc.shape[0])
+        for c in range(ns):
+            for d in range(ns):
+                if not _keep(Q, M, A, B, c, d, tol):
+                    bj += Q[A, B] * Q[c, d] * blk[c, d]
+                if not _keep(Q, M, A, c, B, d, tol):
+                    bk += Q[A, c] * Q[B, d] * blk[c, d]
+        # the bound holds for every Cartesian element of the block; map it
+        # through |T| to the basis functions of the block
+        ta, tb = T[sl[A], slf[A]], T[sl[B], slf[B]]
+        ones = np.ones((sl[A].stop - sl[A].start, sl[B].stop - sl[B].start))
+        shape = ta.T @ ones @ tb
+        out.append((bj[:, None, None] * shape[None], bk[:, None, None] * shape[None]))
+    return out
+
+
+def test_screening_within_per_element_bound_tiny_workload():
+    """Tiny workload, whole matrices: screened minus unscreened J and K,
+    element by element, within the dropped-quartet Schwarz bound, at the
+    production threshold and at a loose one that drops many quartets."""
+    w = synth.config0()
+    b, D = w.basis, w.D
+    J0, K0 = oracle.jk(b, D, 0.0)
+    ns = b.nshells
+    blocks = [(a, c) for a in range(ns) for c in range(ns)]
+    fo = b.func_offsets()
+    for tol in (1e-12, 1e-5):
+        J1, K1 = oracle.jk(b, D, tol)
+        assert oracle.count_quartets(b, D, tol) < oracle.count_quartets(b, D, 0.0) or tol == 1e-12
+        for (a, c), (bj, bk) in zip(blocks, _dropped_bounds(b, D, blocks, tol)):
+            s = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
+            assert np.all(np.abs(J1[s] - J0[s]) <= bj + 1e-14), (tol, a, c)
+            assert np.all(np.abs(K1[s] - K0[s]) <= bk + 1e-14), (tol, a, c)
+
+
+def test_screening_within_per_element_bound_medium_workload():
+    """312-AO workload (16 Laplace pseudo-densities): on sampled shell-pair
+    blocks of every pair class, the screened minus unscreened oracle
+    blocks lie within the per-element dropped-quartet bound, at the
+    production threshold 1e-12 and at a loose 1e-7."""
+    w = synth.config1()
+    b, D = w.basis, w.D
+    l = b.shell_l
+    rng = np.random.default_rng(11)
+    blocks = []
+    for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (0, 2)]:
+        A = np.nonzero(l == la)[0]
+        B = np.nonzero(l == lb)[0]
+        blocks.append((int(A[rng.integers(len(A))]), int(B[rng.integers(len(B))])))
+    ref = oracle.jk_blocks(b, D, blocks, 0.0)
+    for tol in (1e-12, 1e-7):
+        scr = oracle.jk_blocks(b, D, blocks, tol)
+        bounds = _dropped_bounds(b, D, blocks, tol)
+        for (A, B), (Jr, Kr), (Js, Ks), (bj, bk) in zip(blocks, ref, scr, bounds):
+            assert np.all(np.abs(Js - Jr) <= bj + 1e-14), (tol, A, B)
+            assert np.all(np.abs(Ks - Kr) <= bk + 1e-14), (tol, A, B)
+        if tol == 1e-7:
+            # the loose threshold really drops work from these blocks
+            assert any(np.max(np.abs(Js - Jr)) > 0 for (Jr, _), (Js, _) in zip(ref, scr))
