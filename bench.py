@@ -3,16 +3,21 @@
 
 A step is one jk_build call: the whole hot path (density transform, density
 screen, integral and digestion kernels for every class, back-transform) over
-the 16 Laplace pseudo-densities of the 312-AO medium workload (30 atoms,
-18 heavy 3s2p1d + 12 light 2s1p, 3-primitive contractions, Schwarz 1e-12).
-Densities are resident in HBM before the timed region.  One density's J and
-K is one build, so builds/s = 16 x steps / seconds.
+the 40 non-symmetric pseudo-densities (10 Laplace points x 4 transition
+densities) of the 620-AO large workload (52 atoms, 40 heavy 3s2p1d + 12
+light 2s1p, 3-primitive contractions, Schwarz 1e-12), the largest
+single-GPU workload.  Densities are resident in HBM before the timed region.
+One density's J and K is one build, so builds/s = 40 x steps / seconds.  The
+312-AO medium workload (16 densities) is timed the same way and reported
+under "medium".
 
 Prints one JSON line.  Per-kernel durations come from HIP events the library
 records around each integral and digestion launch on the build's stream; the
 dominant kernel's algorithmic flops per launch over its mean launch time give
-the roofline entry.  The CPU baseline times the oracle on a strided sample of
-bra shell pairs on the host cores and scales it by the kept-quartet fraction.
+the roofline entry.  Quartet counts are those the whole screen kept, counted
+on the device.  The CPU baseline times the oracle on strided samples of bra
+shell pairs on all host cores and on one, scales each by the kept-quartet
+fraction, and checks sampled blocks of the timed GPU results against it.
 """
 from __future__ import annotations
 
@@ -64,10 +69,17 @@ def rocprof_name(kernel, g16=True):
             f"{'true' if g16 else 'false'}>(jk::DigestArgs)")
 
 
-def measured_traffic(kernel):
+WORKLOAD_TAG = {"tiny": "tiny28", "medium": "medium312", "large": "large620"}
+
+
+def traffic_path(kernel, workload):
+    return os.path.join(PROFILES, f"{kernel}_{WORKLOAD_TAG[workload]}_traffic.json")
+
+
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when there is none or the kernel sources changed since."""
-    path = os.path.join(PROFILES, f"{kernel}_medium312_traffic.json")
+    path = traffic_path(kernel, workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -124,20 +136,74 @@ def workload(name):
     raise ValueError(name)
 
 
-def cpu_baseline(w, stride):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, stride, stride1, results):
+    """The oracle timed on strided samples of bra shell pairs (all host
+    cores, then one), and sampled shell-pair blocks of the timed GPU
+    results (FP64 and mixed) against the oracle."""
+    import numpy as np
+
     import oracle
     n_cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         n_cores = min(n_cores, int(os.environ["OMP_NUM_THREADS"]))
+
+    def timed(threads, st):
+        oracle.set_threads(max(1, threads))
+        t0 = time.perf_counter()
+        _, _, done, total = oracle.jk_sample(w.basis, w.D, st, 0, 1e-12)
+        dt = time.perf_counter() - t0
+        frac = done / max(total, 1)
+        return w.D.shape[0] * frac / dt, done, total, frac, dt
+
+    v, done, total, frac, dt = timed(n_cores, stride)
+    log(f"cpu baseline: {n_cores} threads {v:.4f} builds/s")
+    v1, done1, _, frac1, dt1 = timed(1, stride1)
+    log(f"cpu baseline: 1 thread {v1:.5f} builds/s")
+    out = {"value": v, "unit": "builds/s", "cores": n_cores, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"bra shell pairs with index % {stride} == 0: {done} of {total} kept quartets "
+                     f"({100 * frac:.2f}%), {dt:.1f} s, scaled by the quartet fraction",
+           "one_thread": {"value": v1, "unit": "builds/s", "cores": 1,
+                          "sample": f"bra shell pairs with index % {stride1} == 0: {done1} kept quartets "
+                                    f"({100 * frac1:.3f}%), {dt1:.1f} s, scaled by the quartet fraction"}}
+    # accuracy of the timed results on sampled blocks, three of every shell-pair class
     oracle.set_threads(max(1, n_cores))
-    t0 = time.perf_counter()
-    _, _, done, total = oracle.jk_sample(w.basis, w.D, stride, 0, 1e-12)
-    dt = time.perf_counter() - t0
-    frac = done / max(total, 1)
-    builds_per_s = w.D.shape[0] * frac / dt
-    return {"value": builds_per_s, "unit": "builds/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"bra shell pairs with index % {stride} == 0: {done} of {total} kept quartets "
-                      f"({100 * frac:.2f}%), {dt:.1f} s, scaled by the quartet fraction"}
+    l = w.basis.shell_l
+    rng = np.random.default_rng(5)
+    blocks = []
+    for la, lb in ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (0, 2)):
+        A, B = np.nonzero(l == la)[0], np.nonzero(l == lb)[0]
+        if len(A) and len(B):
+            blocks += [(int(A[rng.integers(len(A))]), int(B[rng.integers(len(B))])) for _ in range(3)]
+    refs = oracle.jk_blocks(w.basis, w.D, blocks, 1e-12)
+    fo = w.basis.func_offsets()
+    acc = {}
+    for name, (J, K) in results.items():
+        nd = J.shape[0]
+        ej = ek = 0.0
+        dj2, dk2, rj2, rk2 = (np.zeros(nd) for _ in range(4))
+        for (a, c), (Jb, Kb) in zip(blocks, refs):
+            sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
+            ej, ek = max(ej, float(np.max(np.abs(J[sl] - Jb)))), max(ek, float(np.max(np.abs(K[sl] - Kb))))
+            dj2 += np.sum((J[sl] - Jb) ** 2, axis=(1, 2))
+            dk2 += np.sum((K[sl] - Kb) ** 2, axis=(1, 2))
+            rj2 += np.sum(Jb ** 2, axis=(1, 2))
+            rk2 += np.sum(Kb ** 2, axis=(1, 2))
+        acc[name] = {"max_abs_dJ": ej, "max_abs_dK": ek,
+                     "max_rel_frob_dJ": float(np.max(np.sqrt(dj2 / rj2))),
+                     "max_rel_frob_dK": float(np.max(np.sqrt(dk2 / rk2)))}
+    out["accuracy_vs_oracle"] = {"blocks": len(blocks), "per_density_rel_frob_over_blocks": True, **acc}
+    return out
 
 
 def serve_bench(args):
@@ -216,9 +282,11 @@ def serve_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="medium", choices=["tiny", "medium", "large"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
+    ap.add_argument("--no-medium", action="store_true",
+                    help="with the large workload, do not also time the medium one")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--serve", action="store_true",
                     help="serve a Poisson request stream over 16 resident molecules instead")
@@ -226,7 +294,10 @@ def main():
     ap.add_argument("--rate", type=float, default=3.0,
                     help="arrival rate / FP64 one-at-a-time capacity for the throughput phase")
     ap.add_argument("--rate-low", type=float, default=0.7, help="the same for the latency phase")
-    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="oracle sample stride on all cores (0: 64 for the large workload, 8 otherwise)")
+    ap.add_argument("--cpu-stride1", type=int, default=0,
+                    help="oracle sample stride on one core (0: 1024 for the large workload, 128 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="copy this many MiB on the device before timing (counter calibration)")
@@ -235,7 +306,7 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         fd, wd, kern = args.pmc_summary
-        pmc_summary(fd, wd, kern, args.copy_mib, os.path.join(PROFILES, f"{kern}_medium312_traffic.json"))
+        pmc_summary(fd, wd, kern, args.copy_mib, traffic_path(kern, args.workload))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -251,17 +322,7 @@ def main():
     if args.serve:
         serve_bench(args)
         return
-    log(f"workload {args.workload}: generating inputs")
-    w = workload(args.workload)
     dev = torch.device("cuda:0")
-    nd = w.D.shape[0]
-    t0 = time.perf_counter()
-    b = jk.JKBasis(w.basis)
-    setup_s = time.perf_counter() - t0
-    log(f"basis ready: nbf={b.nbf} shells={w.basis.nshells} setup {setup_s:.2f}s")
-    D = torch.tensor(w.D, dtype=torch.float64, device=dev)
-    J = torch.empty_like(D)
-    K = torch.empty_like(D)
     stream = torch.cuda.current_stream(dev)
     if args.copy_mib:
         src = torch.ones(args.copy_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
@@ -271,9 +332,44 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def timed(precision):
-        opts = jk.jk_default_opts(precision=precision)
-        for i in range(args.warmup):
+    result, w, outs = run_workload(args, args.workload, args.steps, args.warmup, args.precision, dev, stream)
+    if args.workload == "large" and not args.no_medium:
+        med, _, _ = run_workload(args, "medium", 2 * args.steps, args.warmup, args.precision, dev, stream)
+        result["medium"] = {k: med[k] for k in ("value", "ms_per_step", "quartets_per_s", "eri_kernels_ms_per_step",
+                                                 "digest_kernels_ms_per_step", "eri_kernels_frac_fp64_peak",
+                                                 "basis_setup_s", "roofline", "mixed", "config")
+                            if k in med}
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on strided samples")
+        st = args.cpu_stride or (64 if args.workload == "large" else 8)
+        st1 = args.cpu_stride1 or (1024 if args.workload == "large" else 128)
+        result["cpu_baseline"] = cpu_baseline(w, st, st1, outs)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+def run_workload(args, name, steps, warmup, precision, dev, stream):
+    """Time `steps` builds of workload `name` (FP64 and/or mixed); returns the
+    JSON record, the workload and the host copies of the last results."""
+    import numpy as np
+    import torch
+
+    from paper_2607_05622_amd import jk
+    log(f"workload {name}: generating inputs")
+    w = workload(name)
+    nd = w.D.shape[0]
+    t0 = time.perf_counter()
+    b = jk.JKBasis(w.basis)
+    setup_s = time.perf_counter() - t0
+    log(f"basis ready: nbf={b.nbf} shells={w.basis.nshells} setup {setup_s:.2f}s")
+    D = torch.tensor(w.D, dtype=torch.float64, device=dev)
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+
+    def timed(prec):
+        opts = jk.jk_default_opts(precision=prec)
+        for i in range(warmup):
             jk.jk_build(b.h, D, J, K, opts, stream)
         torch.cuda.synchronize()
         jk.jk_profile_enable(b.h, True)
@@ -281,7 +377,7 @@ def main():
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
-        for i in range(args.steps):
+        for i in range(steps):
             jk.jk_build(b.h, D, J, K, opts, stream)
         ev1.record(stream)
         torch.cuda.synchronize()
@@ -296,19 +392,21 @@ def main():
                 if r["launches"] > 0:
                     r.update(kernel=f"{kname}_{CLASS_TAGS[c]}", kind=kname)
                     kernels.append(r)
-        log(f"{'mixed' if precision else 'fp64'}: {args.steps} steps, {ms / args.steps:.3f} ms/step")
-        return ms, st, kernels
+        log(f"{name} {'mixed' if prec else 'fp64'}: {steps} steps, {ms / steps:.3f} ms/step")
+        return ms, st, kernels, (J.cpu().numpy(), K.cpu().numpy())
 
     runs = {}
-    if args.precision in ("fp64", "both"):
+    if precision in ("fp64", "both"):
         runs["fp64"] = timed(jk.JK_FP64)
-    if args.precision in ("mixed", "both"):
+    if precision in ("mixed", "both"):
         runs["mixed"] = timed(jk.JK_MIXED)
     head = "fp64" if "fp64" in runs else "mixed"
-    ms, st, kernels = runs[head]
-    ms_step = ms / args.steps
+    ms, st, kernels, _ = runs[head]
+    ms_step = ms / steps
     tot_eri_ms = sum(r["ms"] for r in kernels if r["kind"].startswith("eri_tile"))
     tot_dig_ms = sum(r["ms"] for r in kernels if r["kind"].startswith("digest"))
+    # quartets the whole screen (Schwarz and density parts) kept, counted by the integral kernels
+    kept = sum(r["quartets"] for r in kernels if r["kind"].startswith("eri_tile")) / steps
     dom = max(kernels, key=lambda r: r["ms"])
     per_launch_flops = dom["flops"] / dom["launches"]
     per_launch_ms = dom["ms"] / dom["launches"]
@@ -316,16 +414,16 @@ def main():
     # digestion runs on the FP64 matrix cores, the integral kernels on the FP64
     # vector ALUs; MI355X publishes 78.6 TFLOP/s for both
     dom_bound = "mfma" if dom["kind"].startswith("digest") else "alu"
-    builds_s = nd * args.steps / (ms * 1e-3)
-    quartets_s = st["quartets"] * args.steps / (ms * 1e-3)
+    builds_s = nd * steps / (ms * 1e-3)
+    quartets_s = kept * steps / (ms * 1e-3)
     eri_tflops = sum(r["flops"] for r in kernels if r["kind"].startswith("eri_tile")) / max(tot_eri_ms, 1e-9) / 1e9
     result = {
         "metric": METRIC,
         "value": builds_s,
         "unit": "builds/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -336,11 +434,12 @@ def main():
                                f"{nd} non-symmetric Laplace pseudo-densities, {head} path, Schwarz 1e-12",
                    "nbf": b.nbf, "nd": nd, "precision": head},
         "quartets_per_s": quartets_s,
-        "function_quartets_per_s": st["function_quartets"] * args.steps / (ms * 1e-3),
-        "primitive_quartets_per_s": st["primitive_quartets"] * args.steps / (ms * 1e-3),
-        "quartets_per_build_call": st["quartets"],
-        "eri_kernels_ms_per_step": tot_eri_ms / args.steps,
-        "digest_kernels_ms_per_step": tot_dig_ms / args.steps,
+        "quartets_per_build_call": kept,
+        "quartets_schwarz_lists": st["quartets"],
+        "function_quartets_per_s": st["function_quartets"] * steps / (ms * 1e-3),
+        "primitive_quartets_per_s": st["primitive_quartets"] * steps / (ms * 1e-3),
+        "eri_kernels_ms_per_step": tot_eri_ms / steps,
+        "digest_kernels_ms_per_step": tot_dig_ms / steps,
         "eri_kernels_tflops": eri_tflops,
         "eri_kernels_frac_fp64_peak": eri_tflops / FP64_VALU_PEAK,
         "basis_setup_s": setup_s,
@@ -351,28 +450,34 @@ def main():
             "peak": FP64_VALU_PEAK,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK,
-            "traffic": measured_traffic(dom["kernel"]),
+            "traffic": measured_traffic(dom["kernel"], name),
             "launches": int(dom["launches"]),
             "mean_launch_ms": per_launch_ms,
             "flops_per_launch": per_launch_flops,
         },
-        "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / args.steps, 4)
+        "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / steps, 4)
                                for r in sorted(kernels, key=lambda r: -r["ms"])},
     }
+    outs = {head: runs[head][3]}
     if "mixed" in runs:
-        mms, mst, mk = runs["mixed"]
-        result["mixed"] = {"builds_per_s": nd * args.steps / (mms * 1e-3), "ms_per_step": mms / args.steps,
+        mms, mst, mk, (Jm, Km) = runs["mixed"]
+        outs["mixed"] = (Jm, Km)
+        result["mixed"] = {"builds_per_s": nd * steps / (mms * 1e-3), "ms_per_step": mms / steps,
                            "quartets_fp32_fraction": mst["quartets_fp32"] / max(mst["quartets"], 1),
                            "speedup_vs_fp64": (ms / mms) if head == "fp64" else None,
-                           "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / args.steps, 4)
+                           "kernel_ms_per_step": {r["kernel"]: round(r["ms"] / steps, 4)
                                                   for r in sorted(mk, key=lambda r: -r["ms"])[:12]}}
+        if head == "fp64":
+            J64, K64 = runs["fp64"][3]
+
+            def rel(a, r):
+                return float(np.max(np.sqrt(np.sum((a - r) ** 2, axis=(1, 2)) /
+                                            np.maximum(np.sum(r ** 2, axis=(1, 2)), 1e-300))))
+            result["mixed"]["error_vs_gpu_fp64"] = {
+                "max_abs_dJ": float(np.max(np.abs(Jm - J64))), "max_abs_dK": float(np.max(np.abs(Km - K64))),
+                "max_rel_frob_dJ": rel(Jm, J64), "max_rel_frob_dK": rel(Km, K64)}
     b.close()
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a strided sample")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
-    else:
-        result["cpu_baseline"] = None
-    print(json.dumps(result), flush=True)
+    return result, w, outs
 
 
 if __name__ == "__main__":

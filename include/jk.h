@@ -125,23 +125,42 @@ int jk_build_batch(int32_t nmol, const jk_basis_t* h, const int32_t* nd, const d
 size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t* nd,
                                 const jk_build_opts* o);
 
-/* Schedule autotuning.  Per canonical class the library keeps two launch
- * parameters: seg_max, the length cap of a digestion piece (quartets of one
- * bra pair digested by one workgroup: a run of equal ket shell, cut at the
- * cap; classes of at most 18 functions per quartet pack consecutive runs up
- * to the cap), and g_max, the densities a digestion wave
- * takes at once (16; any of 1, 2, 4, 8 selects 8, which is also used when
- * a build has at most 8 densities).  jk_autotune times
- * every candidate pair on the given build with the event profiler, keeps
- * the fastest per class, applies it process-wide and, if cache_path is not
- * NULL, writes it as JSON keyed by GPU architecture and class;
- * jk_tune_load applies such a file.  Synchronizes o->stream.  Changing the
- * tunables makes later builds regenerate their cached work plans. */
+/* Schedule tunables and autotuning.  Per canonical class (index 0..20) the
+ * library keeps four launch parameters, process-wide:
+ *   seg_max    length cap of a digestion piece (quartets of one bra pair
+ *              digested by one task: a run of equal ket shell, cut at the
+ *              cap; classes of at most 18 functions per quartet pack
+ *              consecutive runs up to the cap), 4..2^20, default 128;
+ *   g_max      densities a digestion task takes at once: 16 (default), or
+ *              any of 1, 2, 4, 8 for 8 (also used when a build has at most 8);
+ *   dig_kernel 1 (default): a workgroup stages each chunk of tiles once for
+ *              waves of different roles; 2: every wave owns a task and all
+ *              its roles (classes of at most 408 functions per quartet;
+ *              others use 1);
+ *   eri_block  quartets (threads) per integral workgroup: 64, 128 or 256
+ *              (default).
+ * The paper launches integral work per realized bucket and notes that the
+ * best mapping depends on the bucket (Sect. 3, "DAG-driven, spill-bounded GPU
+ * chunking"); jk_autotune picks these per class by timing: with the event
+ * profiler it times candidates on the given build (digestion kernel x
+ * density group, then piece length, then integral workgroup size, each around
+ * the best so far), keeps the fastest per class, applies it process-wide and,
+ * if cache_path is not NULL, writes it as JSON keyed by GPU architecture and
+ * class; jk_tune_load applies such a file (absent fields keep defaults).
+ * Synchronizes o->stream.  Changing the tunables makes later builds
+ * regenerate their cached work plans.  JK_EINVAL for values outside the
+ * ranges above. */
+typedef struct {
+    int32_t seg_max;
+    int32_t g_max;
+    int32_t dig_kernel;
+    int32_t eri_block;
+} jk_tune_t;
 int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
                 const jk_build_opts* o, const char* cache_path);
 int jk_tune_load(const char* path);
-int jk_tune_set(int32_t cls, int32_t seg_max, int32_t g_max);
-int jk_tune_get(int32_t cls, int32_t* seg_max, int32_t* g_max);
+int jk_tune_set(int32_t cls, const jk_tune_t* t);
+int jk_tune_get(int32_t cls, jk_tune_t* t);
 
 /* HIP graph of one build, for callers that replay the same build shape
  * (serving loops with fixed per-slot buffers).  jk_graph_create captures
@@ -188,8 +207,10 @@ int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
  * over runs of equal ket shell c), 4 = digestion pass D (K over runs of
  * equal d); 2, 3 and 5 the same for the FP32 tier of JK_MIXED builds;
  * cls = canonical class index 0..20.  out[0] total milliseconds, out[1] launches,
- * out[2] algorithmic flops, out[3] shell quartets, out[4] bytes written
- * (integral tiles) or read (tiles, digestion).  Not for concurrent builds. */
+ * out[2] algorithmic flops of the quartets the whole screen kept (Schwarz and
+ * density parts), out[3] those quartets (counted on the device by the integral
+ * kernels), out[4] bytes written (integral tiles) or read (tiles, digestion).
+ * Not for concurrent builds. */
 int jk_profile_enable(jk_basis_t h, int32_t on);
 int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]);
 

@@ -2,6 +2,7 @@
 // class index with -DJK_CLASS_INDEX=n so the generated recurrences build in
 // parallel.  Defines launch_eri_tile_c<n> and launch_digest_c<n>.
 #include "jk_digest.h"
+#include "jk_digest2.h"
 
 #ifndef JK_CLASS_INDEX
 #error "compile with -DJK_CLASS_INDEX=<0..20>"
@@ -18,15 +19,32 @@ constexpr long long kEriGridCap = 256 * 8;
 
 template <class C, typename R>
 hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
-    const unsigned g = static_cast<unsigned>(a.nblocks < kEriGridCap ? a.nblocks : kEriGridCap);
-    hipLaunchKernelGGL((k_eri_tile<C, R>), dim3(g), dim3(256), 0, s, a);
+    const int block = (a.block == 64 || a.block == 128) ? a.block : 256;
+    const long long cap = kEriGridCap * (256 / block);
+    const unsigned g = static_cast<unsigned>(a.nblocks < cap ? a.nblocks : cap);
+    hipLaunchKernelGGL((k_eri_tile<C, R>), dim3(g), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-// Digestion: one workgroup per task; pass C has a J wave and one K wave per
-// density form, pass D one K wave per density form.
+// Digestion.  kernel 2: wave-private tasks (jk_digest2.h), four per
+// workgroup, for classes of at most 408 functions per quartet.  Otherwise
+// one workgroup per task; pass C has a J wave and one K wave per density
+// form, pass D one K wave per density form.
 template <int la, int lb, int lc, int ld, typename TT>
-hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16) {
+hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16, int kernel) {
+    constexpr int nf = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
+    if constexpr (dig2_class(la, lb, lc, ld, nf)) if (kernel == 2) {
+        const dim3 grid(8 * ((a.nblocks / 8 + kDig2Waves - 1) / kDig2Waves));
+        const dim3 block(64 * kDig2Waves);
+        if (pass == 0) {
+            if (g16) hipLaunchKernelGGL((k_digest2_c<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_digest2_c<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+        } else {
+            if (g16) hipLaunchKernelGGL((k_digest2_d<la, lb, lc, ld, TT, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_digest2_d<la, lb, lc, ld, TT, false>), grid, block, 0, s, a);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(a.nblocks);
     if (pass == 0) {
         if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(192), 0, s, a);
@@ -43,9 +61,10 @@ hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g
         return fp32 ? launch_eri_tpl<Eri##tag<float>, float>(a, s)                                 \
                     : launch_eri_tpl<Eri##tag<double>, double>(a, s);                              \
     }                                                                                              \
-    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16) { \
-        return fp32 ? launch_digest_tpl<la, lb, lc, ld, float>(a, s, pass, g16)                    \
-                    : launch_digest_tpl<la, lb, lc, ld, double>(a, s, pass, g16);                  \
+    hipError_t JK_PASTE(launch_digest_c, idx)(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16, \
+                                              int kernel) {                                        \
+        return fp32 ? launch_digest_tpl<la, lb, lc, ld, float>(a, s, pass, g16, kernel)            \
+                    : launch_digest_tpl<la, lb, lc, ld, double>(a, s, pass, g16, kernel);          \
     }
 
 #define JK_SELECT(idx, tag, la, lb, lc, ld) JK_SELECT_##idx(idx, tag, la, lb, lc, ld)

@@ -307,7 +307,7 @@ __device__ __forceinline__ PairInfo load_pair(gptr<const PairInfo> p) {
 // large for exactly the small, distant quartets of this tier; the tile is
 // stored as float).
 template <class C, typename R>
-__device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, const EriItem& it, long long q) {
+__device__ __forceinline__ bool eri_one(const EriTileArgs& a, const MolDesc& m, const EriItem& it, long long q) {
     const long long bkw = glob(reinterpret_cast<const long long*>(it.quartets))[q];   // (bra, ket) pair ids
     const PairInfo P = load_pair(glob(m.pairs) + static_cast<int>(bkw & 0xffffffff));
     const PairInfo Q = load_pair(glob(m.pairs) + static_cast<int>(bkw >> 32));
@@ -316,7 +316,7 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
     if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
         for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
-        return;
+        return false;
     }
     using C64 = typename C::template With<double>;
     double acc[C::NACC];
@@ -338,6 +338,7 @@ __device__ __forceinline__ void eri_one(const EriTileArgs& a, const MolDesc& m, 
                   }
               });
     C64::hrr(acc, P.AB, Q.AB, [&](int f, double v) { out[static_cast<long long>(f) * nq] = static_cast<R>(v); });
+    return true;
 }
 
 // High angular momentum: passes over groups of bra components.  Each pass
@@ -373,7 +374,7 @@ __device__ __forceinline__ void eri_split_pass(const EriTileArgs& a, const MolDe
 }
 
 template <class C, typename R>
-__device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDesc& m, const EriItem& it,
+__device__ __forceinline__ bool eri_one_split(const EriTileArgs& a, const MolDesc& m, const EriItem& it,
                                               long long q) {
     const long long bkw = glob(reinterpret_cast<const long long*>(it.quartets))[q];   // (bra, ket) pair ids
     const PairInfo P = load_pair(glob(m.pairs) + static_cast<int>(bkw & 0xffffffff));
@@ -383,7 +384,7 @@ __device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDes
     if (!keep_quartet(P, Q, m.dmax, m.ns, a.tol)) {
 #pragma unroll 1
         for (int f = 0; f < C::NF; ++f) out[static_cast<long long>(f) * nq] = R(0);
-        return;
+        return false;
     }
     // (e0|cd) in FP64 in both tiers: the item's scratch region holds NF x n doubles
     const gptr<double> scr = glob(static_cast<double*>(a.scratch)) + it.tile_off + q;
@@ -394,6 +395,7 @@ __device__ __forceinline__ void eri_one_split(const EriTileArgs& a, const MolDes
         C64::hrrab([&](int e) -> double { return scr[static_cast<long long>(e * C::NCD + cd) * nq]; }, P.AB,
                    [&](int ab, double v) { out[static_cast<long long>(ab * C::NCD + cd) * nq] = static_cast<R>(v); });
     }
+    return true;
 }
 
 // Minimum waves per SIMD an integral kernel is compiled for: 2 where timing
@@ -414,10 +416,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(eri_waves<C
     for (long long blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
         const EriItem it = a.items[find_item(a.items, a.nitems, blk)];
         const long long q = (blk - it.blk0) * blockDim.x + threadIdx.x;
-        if (q >= it.n) continue;
-        const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
-        if constexpr (C::kSplit) eri_one_split<C, R>(a, m, it, q);
-        else eri_one<C, R>(a, m, it, q);
+        bool kept = false;
+        if (q < it.n) {
+            const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
+            if constexpr (C::kSplit) kept = eri_one_split<C, R>(a, m, it, q);
+            else kept = eri_one<C, R>(a, m, it, q);
+        }
+        if (a.kept) {
+            // measurement: quartets the whole screen kept, one atomic per wavefront
+            const unsigned long long mask = __ballot(kept);
+            if ((threadIdx.x & 63) == 0 && mask) atomicAdd(a.kept, static_cast<unsigned long long>(__popcll(mask)));
+        }
     }
 }
 

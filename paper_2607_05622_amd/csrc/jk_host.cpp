@@ -54,7 +54,10 @@ constexpr double kPi = 3.14159265358979323846;
 // recurrences multiply in.  1e-6 of the default quartet threshold: what is
 // dropped stays far below FP64 rounding of the contracted integrals.
 constexpr double kPrimPairTol = 1e-18;
-constexpr long long kTileCapElems = 32ll << 20;   // 256 MB FP64 work buffer cap
+// Integral work buffer cap (elements): 2 GB of FP64 tiles, so a launch of a
+// high angular momentum class holds a few hundred thousand quartets, many
+// waves per SIMD at its one-wave occupancy.
+constexpr long long kTileCapElems = 256ll << 20;
 
 double dfact(int n) {
     double r = 1.0;
@@ -106,12 +109,15 @@ int class_nf(int cls) { return kClassCost[cls].nfunc; }
 
 // Schedule tunables per class (process-wide; chosen by jk_autotune): the
 // length cap of a digestion part (a run of one bra pair's quartets with one
-// ket shell, digested by one workgroup; longer runs are cut) and the
-// densities a digestion workgroup takes at once (16, or 8 when g_max < 16 or
-// the batch has at most 8 densities).
+// ket shell, digested by one task; longer runs are cut), the densities a
+// digestion task takes at once (16, or 8 when g_max < 16 or the batch has at
+// most 8 densities), the digestion kernel (1: workgroup-shared chunks, 2:
+// wave-private tasks) and the quartets per integral workgroup.
 struct Tune {
     int seg_max = 128;
     int g_max = 16;
+    int dig_kernel = 1;
+    int eri_block = 256;
 };
 std::mutex g_tune_mu;
 Tune g_tune[kNumClass];
@@ -205,6 +211,9 @@ struct jk_basis_s {
     bool profiling = false;
     std::vector<ProfRec> prof;
     double prof_acc[6][kNumClass][5] = {};
+    // per tier and class: quartets the whole screen kept in profiled builds
+    // (device counters, folded and cleared by jk_profile_read)
+    unsigned long long* d_kept = nullptr;
 
     ~jk_basis_s() {
         int cur = 0;
@@ -227,6 +236,7 @@ struct jk_basis_s {
             (void)hipFree(l.dev_parts[1]);
         }
         for (auto* p : retired) (void)hipFree(p);
+        (void)hipFree(d_kept);
         for (auto& r : prof) {
             (void)hipEventDestroy(r.e0);
             (void)hipEventDestroy(r.e1);
@@ -277,6 +287,7 @@ int eval_tiles(jk_basis_s* h, int cls, const std::vector<int2>& quartets, std::v
         a.items = ditem;
         a.nitems = 1;
         a.nblocks = (nq + 255) / 256;
+        a.block = 256;
         a.mol0.pairs = h->d_pairs;
         a.mol0.prims = h->d_prims;
         a.mol0.pslots = h->pslots;
@@ -592,7 +603,7 @@ int ensure_lists(jk_basis_s* h, double tol, double bound) {
 // One class and tier of a build: an integral launch over eri items and two
 // digestion launches (pass C, pass D) over dig items, all molecules together.
 struct LaunchRec {
-    int cls = 0, fp32 = 0, g16 = 1;
+    int cls = 0, fp32 = 0, g16 = 1, dig_kernel = 1, eri_block = 256;
     int eri0 = 0, neri = 0;
     long long eri_blocks = 0;
     int dig0[2] = {0, 0}, ndig[2] = {0, 0};
@@ -670,6 +681,8 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                 fresh.cls = c;
                 fresh.fp32 = fp32;
                 fresh.g16 = g16;
+                fresh.dig_kernel = tn.dig_kernel;
+                fresh.eri_block = tn.eri_block;
                 fresh.eri0 = static_cast<int>(wp.eri.size());
                 fresh.dig0[0] = static_cast<int>(wp.dig[0].size());
                 fresh.dig0[1] = static_cast<int>(wp.dig[1].size());
@@ -688,7 +701,9 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                 const long long nq_tier = mixed ? (tier ? CL.count - CL.n64 : CL.n64) : CL.count;
                 const double prim_tier = mixed ? CL.prim_quartets[tier] : CL.prim_quartets[0] + CL.prim_quartets[1];
                 const double prim_avg = prim_tier / static_cast<double>(std::max<long long>(nq_tier, 1));
-                const int ngroups = dens_stride(nd) / G;
+                // density groups holding at least one of the nd densities (the
+                // padding of the density stride beyond them is never digested)
+                const int ngroups = (nd + G - 1) / G;
                 for (int b0 = bbeg; b0 < bend;) {
                     const long long q0 = CL.blocks[b0].x;
                     int b1 = b0;
@@ -709,7 +724,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     e.mol = static_cast<int>(mi);
                     wp.eri.push_back(e);
                     L.neri++;
-                    L.eri_blocks += (n + 255) / 256;
+                    L.eri_blocks += (n + tn.eri_block - 1) / tn.eri_block;
                     for (int k = b0; k < b1; ++k) {
                         const int x = static_cast<int>(std::min_element(xwork, xwork + 8) - xwork);
                         xwork[x] += static_cast<double>(CL.blocks[k].y) * ngroups;
@@ -1103,6 +1118,8 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         ea.tol = o->schwarz_tol;
         ea.tiles = tiles;
         ea.scratch = scratch;
+        ea.kept = (prof && prof->profiling && prof->d_kept) ? prof->d_kept + L.fp32 * kNumClass + L.cls : nullptr;
+        ea.block = L.eri_block;
         DigestArgs da[2]{};
         for (int ps = 0; ps < 2; ++ps) {
             da[ps].items = d_dig[ps] + L.dig0[ps];
@@ -1125,9 +1142,9 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         }
         e = launch_eri_tile(L.cls, ea, s, L.fp32);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
-        if (e == hipSuccess) e = launch_digest(L.cls, da[0], s, L.fp32, 0, L.g16);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[0], s, L.fp32, 0, L.g16, L.dig_kernel);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[2], s);
-        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16, L.dig_kernel);
         if (e == hipSuccess && timed) e = hipEventRecord(ev[3], s);
         if (e != hipSuccess) return e;
         if (timed) {
@@ -1466,22 +1483,28 @@ int jk_build_batch(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const 
     return JK_OK;
 }
 
-int jk_tune_set(int32_t cls, int32_t seg_max, int32_t g_max) {
-    if (cls < 0 || cls >= kNumClass || seg_max < 1 || seg_max > (1 << 20) || !(g_max == 1 || g_max == 2 ||
-        g_max == 4 || g_max == 8 || g_max == 16))
+int jk_tune_set(int32_t cls, const jk_tune_t* t) {
+    if (cls < 0 || cls >= kNumClass || !t || t->seg_max < 4 || t->seg_max > (1 << 20) ||
+        !(t->g_max == 1 || t->g_max == 2 || t->g_max == 4 || t->g_max == 8 || t->g_max == 16) ||
+        !(t->dig_kernel == 1 || t->dig_kernel == 2) ||
+        !(t->eri_block == 64 || t->eri_block == 128 || t->eri_block == 256))
         return fail(JK_EINVAL, "jk_tune_set: bad arguments");
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[cls].seg_max = seg_max;
-    g_tune[cls].g_max = g_max;
+    g_tune[cls].seg_max = t->seg_max;
+    g_tune[cls].g_max = t->g_max;
+    g_tune[cls].dig_kernel = t->dig_kernel;
+    g_tune[cls].eri_block = t->eri_block;
     ++g_tune_gen;
     return JK_OK;
 }
 
-int jk_tune_get(int32_t cls, int32_t* seg_max, int32_t* g_max) {
-    if (cls < 0 || cls >= kNumClass || !seg_max || !g_max) return fail(JK_EINVAL, "jk_tune_get: bad arguments");
+int jk_tune_get(int32_t cls, jk_tune_t* t) {
+    if (cls < 0 || cls >= kNumClass || !t) return fail(JK_EINVAL, "jk_tune_get: bad arguments");
     std::lock_guard<std::mutex> g(g_tune_mu);
-    *seg_max = g_tune[cls].seg_max;
-    *g_max = g_tune[cls].g_max;
+    t->seg_max = g_tune[cls].seg_max;
+    t->g_max = g_tune[cls].g_max;
+    t->dig_kernel = g_tune[cls].dig_kernel;
+    t->eri_block = g_tune[cls].eri_block;
     return JK_OK;
 }
 
@@ -1501,15 +1524,22 @@ int jk_tune_load(const char* path) {
     int applied = 0;
     size_t pos = 0;
     while ((pos = txt.find("\"class\":", pos)) != std::string::npos) {
-        int cls = -1, seg = 0, gm = 0;
+        int cls = -1;
         const size_t end = txt.find('}', pos);
         const std::string ent = txt.substr(pos, end - pos);
         if (std::sscanf(ent.c_str(), "\"class\": %d", &cls) == 1) {
-            const size_t ps = ent.find("\"seg_max\":"), pg = ent.find("\"g_max\":");
-            if (ps != std::string::npos && pg != std::string::npos &&
-                std::sscanf(ent.c_str() + ps, "\"seg_max\": %d", &seg) == 1 &&
-                std::sscanf(ent.c_str() + pg, "\"g_max\": %d", &gm) == 1 && jk_tune_set(cls, seg, gm) == JK_OK)
-                ++applied;
+            // every field optional but the class; absent ones keep their defaults
+            jk_tune_t t{128, 16, 1, 256};
+            auto field = [&](const char* key, int32_t& v) {
+                const size_t q = ent.find(key);
+                int x;
+                if (q != std::string::npos && std::sscanf(ent.c_str() + q + std::strlen(key), " %d", &x) == 1) v = x;
+            };
+            field("\"seg_max\":", t.seg_max);
+            field("\"g_max\":", t.g_max);
+            field("\"dig_kernel\":", t.dig_kernel);
+            field("\"eri_block\":", t.eri_block);
+            if (cls >= 0 && cls < kNumClass && jk_tune_set(cls, &t) == JK_OK) ++applied;
         }
         pos = end == std::string::npos ? txt.size() : end;
     }
@@ -1519,48 +1549,67 @@ int jk_tune_load(const char* path) {
 int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o,
                 const char* cache_path) {
     if (!h || !o || nd < 1 || !D || !J || !K) return fail(JK_EINVAL, "jk_autotune: bad arguments");
-    static const int kSeg[] = {16, 32, 64, 128, 256};
-    static const int kG[] = {8, 16};
-    double best_ms[kNumClass];
-    Tune best[kNumClass];
-    for (int c = 0; c < kNumClass; ++c) best_ms[c] = 1e300;
     jk_build_opts oo = *o;
     hipStream_t s = static_cast<hipStream_t>(o->stream);
-    for (int si : kSeg)
-        for (int gi : kG) {
-            for (int c = 0; c < kNumClass; ++c) {
-                int rc = jk_tune_set(c, si, gi);
-                if (rc) return rc;
+    jk_tune_t best[kNumClass];
+    double best_ms[kNumClass];
+    for (int c = 0; c < kNumClass; ++c) {
+        int rc = jk_tune_get(c, &best[c]);
+        if (rc) return rc;
+        best_ms[c] = 1e300;
+    }
+    // times one candidate per class (every class set at once: the classes'
+    // launches are separate, so each class's time is its own); keeps the best
+    auto trial = [&](auto&& make) -> int {
+        jk_tune_t cand[kNumClass];
+        for (int c = 0; c < kNumClass; ++c) {
+            cand[c] = best[c];
+            make(c, cand[c]);
+            int rc = jk_tune_set(c, &cand[c]);
+            if (rc) return rc;
+        }
+        int rc = jk_build(h, nd, D, J, K, &oo);   // warm-up: lists, plans
+        if (rc) return rc;
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(JK_EDEVICE, "jk_autotune: sync failed");
+        if ((rc = jk_profile_enable(h, 1))) return rc;
+        for (int r = 0; r < 2 && !rc; ++r) rc = jk_build(h, nd, D, J, K, &oo);
+        jk_profile_enable(h, 0);
+        if (rc) return rc;
+        for (int c = 0; c < kNumClass; ++c) {
+            double tot = 0, v[5];
+            for (int kind = 0; kind < 6; ++kind) {
+                if ((rc = jk_profile_read(h, kind, c, v))) return rc;
+                tot += v[0];
             }
-            int rc = jk_build(h, nd, D, J, K, &oo);   // warm-up: lists, plans
-            if (rc) return rc;
-            if (hipStreamSynchronize(s) != hipSuccess) return fail(JK_EDEVICE, "jk_autotune: sync failed");
-            jk_profile_enable(h, 1);
-            for (int r = 0; r < 2 && !rc; ++r) rc = jk_build(h, nd, D, J, K, &oo);
-            jk_profile_enable(h, 0);
-            if (rc) return rc;
-            for (int c = 0; c < kNumClass; ++c) {
-                double tot = 0, v[5];
-                for (int kind = 0; kind < 6; ++kind) {
-                    if ((rc = jk_profile_read(h, kind, c, v))) return rc;
-                    tot += v[0];
-                }
-                if (tot > 0 && tot < best_ms[c]) {
-                    best_ms[c] = tot;
-                    best[c].seg_max = si;
-                    best[c].g_max = gi;
-                }
+            if (tot > 0 && tot < best_ms[c]) {
+                best_ms[c] = tot;
+                best[c] = cand[c];
             }
         }
-    for (int c = 0; c < kNumClass; ++c) jk_tune_set(c, best[c].seg_max, best[c].g_max);
+        return JK_OK;
+    };
+    // coordinate search: digestion kernel x density group, then piece
+    // length, then integral workgroup size, each around the best so far
+    int rc;
+    for (int k : {1, 2})
+        for (int g : {16, 8})
+            if ((rc = trial([&](int, jk_tune_t& t) { t.dig_kernel = k; t.g_max = g; }))) return rc;
+    for (int seg : {32, 64, 128, 256})
+        if ((rc = trial([&](int, jk_tune_t& t) { t.seg_max = seg; }))) return rc;
+    for (int blk : {64, 128, 256})
+        if ((rc = trial([&](int, jk_tune_t& t) { t.eri_block = blk; }))) return rc;
+    for (int c = 0; c < kNumClass; ++c)
+        if ((rc = jk_tune_set(c, &best[c]))) return rc;
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "w");
         if (!f) return fail(JK_EINVAL, "jk_autotune: cannot write %s", cache_path);
         std::fprintf(f, "{\"arch\": \"%s\", \"nd\": %d, \"nbf\": %d, \"entries\": [\n", kArch, nd, h->nf);
         for (int c = 0; c < kNumClass; ++c)
-            std::fprintf(f, "  {\"class\": %d, \"seg_max\": %d, \"g_max\": %d, \"ms_per_build\": %.5f}%s\n", c,
-                         best[c].seg_max, best[c].g_max, best_ms[c] < 1e299 ? best_ms[c] / 2 : -1.0,
-                         c + 1 < kNumClass ? "," : "");
+            std::fprintf(f,
+                         "  {\"class\": %d, \"seg_max\": %d, \"g_max\": %d, \"dig_kernel\": %d, \"eri_block\": %d, "
+                         "\"ms_per_build\": %.5f}%s\n",
+                         c, best[c].seg_max, best[c].g_max, best[c].dig_kernel, best[c].eri_block,
+                         best_ms[c] < 1e299 ? best_ms[c] / 2 : -1.0, c + 1 < kNumClass ? "," : "");
         std::fprintf(f, "]}\n");
         std::fclose(f);
     }
@@ -1637,7 +1686,14 @@ void jk_graph_destroy(jk_graph_t g) {
 
 int jk_profile_enable(jk_basis_t h, int32_t on) {
     if (!h || (on != 0 && on != 1)) return fail(JK_EINVAL, "jk_profile_enable: bad arguments");
+    DeviceGuard dg;
+    int rc = dg.ok(h->device);
+    if (rc) return rc;
     std::lock_guard<std::mutex> g(h->mu);
+    if (on && !h->d_kept) {
+        HIPC(hipMalloc(&h->d_kept, 2 * kNumClass * sizeof(unsigned long long)));
+        HIPC(hipMemset(h->d_kept, 0, 2 * kNumClass * sizeof(unsigned long long)));
+    }
     h->profiling = on != 0;
     return JK_OK;
 }
@@ -1650,15 +1706,37 @@ int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]) {
     // digestion record is the end event of its integral record, so events
     // are destroyed only once both uses are folded
     std::vector<hipEvent_t> dead;
+    for (auto& r : h->prof) HIPC(hipEventSynchronize(r.e1));
+    // the kept counters cover exactly the pending records: scale their
+    // quartet and flop counts (list quartets) to the quartets the whole
+    // screen kept, per tier and class
+    double ratio[2][kNumClass];
+    for (auto& v : ratio)
+        for (double& x : v) x = 1.0;
+    if (h->d_kept && !h->prof.empty()) {
+        DeviceGuard dg;
+        int rc = dg.ok(h->device);
+        if (rc) return rc;
+        unsigned long long kept[2 * kNumClass];
+        HIPC(hipMemcpy(kept, h->d_kept, sizeof(kept), hipMemcpyDeviceToHost));
+        HIPC(hipMemset(h->d_kept, 0, sizeof(kept)));
+        double listed[2][kNumClass] = {};
+        for (auto& r : h->prof)
+            if (r.kind == 0 || r.kind == 2) listed[r.kind / 2][r.cls] += r.quartets;
+        for (int t = 0; t < 2; ++t)
+            for (int c = 0; c < kNumClass; ++c)
+                if (listed[t][c] > 0) ratio[t][c] = static_cast<double>(kept[t * kNumClass + c]) / listed[t][c];
+    }
     for (auto& r : h->prof) {
-        HIPC(hipEventSynchronize(r.e1));
         float ms = 0.0f;
         HIPC(hipEventElapsedTime(&ms, r.e0, r.e1));
+        const int tier = (r.kind == 2 || r.kind == 3 || r.kind == 5) ? 1 : 0;
+        const double f = ratio[tier][r.cls];
         double* a = h->prof_acc[r.kind][r.cls];
         a[0] += ms;
         a[1] += 1;
-        a[2] += r.flops;
-        a[3] += r.quartets;
+        a[2] += r.flops * f;
+        a[3] += r.quartets * f;
         a[4] += r.bytes;
         dead.push_back(r.e0);
         dead.push_back(r.e1);

@@ -105,11 +105,11 @@ hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s, int fp3
     }
 }
 
-hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16) {
+hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16, int kernel) {
     if (a.nblocks == 0) return hipSuccess;
     switch (cls) {
 #define JK_CASE(n) \
-    case n: return launch_digest_c##n(a, s, fp32, pass, g16);
+    case n: return launch_digest_c##n(a, s, fp32, pass, g16, kernel);
         JK_FOR_CLASS_INDEX(JK_CASE)
 #undef JK_CASE
         default: return hipErrorInvalidValue;

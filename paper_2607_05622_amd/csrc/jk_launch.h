@@ -64,6 +64,8 @@ struct EriTileArgs {
     double tol;
     void* tiles;            // double (FP64 tier) or float (FP32 tier)
     void* scratch;          // (e0|cd) of pass-evaluated classes, same offsets as tiles
+    unsigned long long* kept;  // when not null: += quartets kept by the whole screen (measurement)
+    int block;              // threads (quartets) per workgroup: 64, 128 or 256; blocks of the items count these
 };
 
 // Digestion work of one bra pair (a "block": the bra pair's quartets of one
@@ -106,15 +108,17 @@ struct DigestArgs {
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 #define JK_DECLARE(n)                                                                 \
     hipError_t launch_eri_tile_c##n(const EriTileArgs& a, hipStream_t s, int fp32); \
-    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16);
+    hipError_t launch_digest_c##n(const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16, int kernel);
 JK_FOR_CLASS_INDEX(JK_DECLARE)
 #undef JK_DECLARE
 
 // fp32 = 1: the FP32 tier (float recurrences and tiles)
 hipError_t launch_eri_tile(int cls, const EriTileArgs& a, hipStream_t s, int fp32 = 0);
 // pass 0: C-order digestion (J, K rows/columns of c), pass 1: D-order (K of d);
-// g16 = 1: 16 densities per wave task, 0: 8
-hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16);
+// g16 = 1: 16 densities per wave task, 0: 8; kernel 1: workgroup-shared
+// chunks (jk_digest.h), 2: wave-private tasks (jk_digest2.h) where compiled
+// for the class, else 1
+hipError_t launch_digest(int cls, const DigestArgs& a, hipStream_t s, int fp32, int pass, int g16, int kernel);
 hipError_t launch_sph2cart(const double* D, int nd, int nf, const CartMap* cmap, int nc, int ndp, double* Dc,
                            hipStream_t s);
 hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc, int nd, int nf,

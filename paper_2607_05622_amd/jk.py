@@ -36,6 +36,11 @@ class jk_basis_desc(ctypes.Structure):
                 ("spherical", ctypes.c_int32)]
 
 
+class jk_tune_t(ctypes.Structure):
+    _fields_ = [("seg_max", ctypes.c_int32), ("g_max", ctypes.c_int32), ("dig_kernel", ctypes.c_int32),
+                ("eri_block", ctypes.c_int32)]
+
+
 class jk_build_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("schwarz_tol", ctypes.c_double),
                 ("fp32_bound", ctypes.c_double), ("want_j", ctypes.c_int32), ("want_k", ctypes.c_int32),
@@ -87,9 +92,9 @@ def load(path: str = LIB_PATH):
     lib.jk_autotune.restype = c_int
     lib.jk_tune_load.argtypes = [ctypes.c_char_p]
     lib.jk_tune_load.restype = c_int
-    lib.jk_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.jk_tune_set.argtypes = [ctypes.c_int32, ctypes.POINTER(jk_tune_t)]
     lib.jk_tune_set.restype = c_int
-    lib.jk_tune_get.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.jk_tune_get.argtypes = [ctypes.c_int32, ctypes.POINTER(jk_tune_t)]
     lib.jk_tune_get.restype = c_int
     lib.jk_graph_create.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts),
                                     ctypes.POINTER(ctypes.c_void_p)]
@@ -271,14 +276,15 @@ def jk_tune_load(path: str) -> None:
     _check(load().jk_tune_load(path.encode()))
 
 
-def jk_tune_set(cls: int, seg_max: int, g_max: int) -> None:
-    _check(load().jk_tune_set(cls, seg_max, g_max))
+def jk_tune_set(cls: int, seg_max: int = 128, g_max: int = 16, dig_kernel: int = 1, eri_block: int = 256) -> None:
+    t = jk_tune_t(seg_max, g_max, dig_kernel, eri_block)
+    _check(load().jk_tune_set(cls, ctypes.byref(t)))
 
 
-def jk_tune_get(cls: int) -> tuple:
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(load().jk_tune_get(cls, ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+def jk_tune_get(cls: int) -> dict:
+    t = jk_tune_t()
+    _check(load().jk_tune_get(cls, ctypes.byref(t)))
+    return dict(seg_max=t.seg_max, g_max=t.g_max, dig_kernel=t.dig_kernel, eri_block=t.eri_block)
 
 
 def jk_graph_create(h, D, J, K, opts: jk_build_opts) -> int:

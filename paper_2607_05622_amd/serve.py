@@ -31,6 +31,13 @@ import torch
 from . import jk
 
 
+class _Shape:
+    """Stands in for a density tensor where only its count is needed."""
+
+    def __init__(self, nd):
+        self.shape = (nd,)
+
+
 @dataclass
 class Request:
     index: int
@@ -87,18 +94,28 @@ class JKServer:
                             torch.empty(per_slot, dtype=torch.uint8, device=self.dev)) for _ in range(n_slots)]
         self.slot_bytes = per_slot
         self.peak_admitted = 0
+        self._single = {}           # (mol, nd) -> workspace of that request alone
+        self.sched_s = 0.0          # host time spent choosing and sizing launches
 
     # ------------------------------------------------------------- sizes --
     def workspace_bytes(self, reqs) -> int:
+        """Exact workspace of one batched launch of `reqs` (plans the batch)."""
         hs = [self.handles[r.mol].h for r in reqs]
         return jk.jk_batch_workspace_bytes(hs, [r.nd for r in reqs], self.opts)
+
+    def single_bytes(self, mol, nd) -> int:
+        """Workspace of one request alone, cached per (molecule, nd)."""
+        key = (mol, nd)
+        if key not in self._single:
+            self._single[key] = self.workspace_bytes([Request(-1, 0.0, mol, _Shape(nd))])
+        return self._single[key]
 
     def graph_bytes(self, mol, nd_bucket) -> int:
         n = self.nbf[mol]
         return jk.jk_workspace_bytes(self.handles[mol].h, nd_bucket, self.opts) + 3 * nd_bucket * n * n * 8
 
     def fits_alone(self, req) -> bool:
-        return self.workspace_bytes([req]) <= self.slot_bytes
+        return self.single_bytes(req.mol, req.nd) <= self.slot_bytes
 
     # ------------------------------------------------------------ graphs --
     def _graph(self, slot: _Slot, mol: int, ndb: int):
@@ -160,9 +177,8 @@ class JKServer:
                     self._done(slot, reqs)
                     return
             o = jk.jk_default_opts(precision=self.opts.precision)
-            ws = self.workspace_bytes(reqs)
             o.workspace = slot.arena.data_ptr()
-            o.workspace_bytes = ws
+            o.workspace_bytes = self.slot_bytes
             jk.jk_build_batch([self.handles[r.mol].h for r in reqs], [r.D for r in reqs],
                               [r.J for r in reqs], [r.K for r in reqs], o, s)
         self._done(slot, reqs)
@@ -207,13 +223,26 @@ class JKServer:
                     if on_progress:
                         on_progress(done, n)
                 if not slot.busy and queue:
+                    # admission in arrival order: requests join while the sum of
+                    # their alone-workspaces fits the slot (cached per molecule
+                    # and density count); one exact sizing of the launch, which
+                    # sheds the newest requests in the rare case it does not fit
+                    ts = time.perf_counter()
                     batch = [queue[0]]
+                    est = self.single_bytes(queue[0].mol, queue[0].nd)
                     for r in queue[1:]:
                         if len(batch) >= self.max_batch:
                             break
-                        if self.workspace_bytes(batch + [r]) <= self.slot_bytes:
-                            batch.append(r)
+                        e = self.single_bytes(r.mol, r.nd)
+                        if est + e > self.slot_bytes:
+                            break
+                        batch.append(r)
+                        est += e
                     ws = self.workspace_bytes(batch)
+                    while ws > self.slot_bytes and len(batch) > 1:
+                        batch.pop()
+                        ws = self.workspace_bytes(batch)
+                    self.sched_s += time.perf_counter() - ts
                     self.peak_admitted = max(self.peak_admitted, ws)
                     for r in batch:
                         queue.remove(r)
@@ -225,7 +254,9 @@ class JKServer:
             if not progressed:
                 time.sleep(5e-5)
         torch.cuda.synchronize(self.dev)
-        return summarize(reqs)
+        out = summarize(reqs)
+        out["host_sched_ms"] = self.sched_s * 1e3
+        return out
 
     def close(self):
         for slot in self.slots:

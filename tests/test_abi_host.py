@@ -104,22 +104,26 @@ def test_header_constants_match_binding():
 def test_tune_table_and_cache(tmp_path, lib):
     old = [jk.jk_tune_get(c) for c in range(21)]
     try:
-        jk.jk_tune_set(3, 512, 8)
-        assert jk.jk_tune_get(3) == (512, 8)
-        for bad in [(-1, 256, 4), (21, 256, 4), (0, 0, 4), (0, 256, 3), (0, 256, 32)]:
+        jk.jk_tune_set(3, 512, 8, 2, 64)
+        assert jk.jk_tune_get(3) == dict(seg_max=512, g_max=8, dig_kernel=2, eri_block=64)
+        for bad in [(-1, 256, 4), (21, 256, 4), (0, 0, 4), (0, 256, 3), (0, 256, 32), (0, 256, 16, 3),
+                    (0, 256, 16, 1, 32), (0, 256, 16, 1, 512)]:
             with pytest.raises(jk.JKError):
                 jk.jk_tune_set(*bad)
         p = tmp_path / "tune.json"
         p.write_text('{"arch": "gfx950", "entries": [\n'
-                     '  {"class": 0, "seg_max": 2048, "g_max": 16, "ms_per_build": 0.1},\n'
+                     '  {"class": 0, "seg_max": 2048, "g_max": 16, "dig_kernel": 2, "eri_block": 128,'
+                     ' "ms_per_build": 0.1},\n'
                      '  {"class": 20, "seg_max": 128, "g_max": 4, "ms_per_build": 0.2}\n]}\n')
         jk.jk_tune_load(str(p))
-        assert jk.jk_tune_get(0) == (2048, 16) and jk.jk_tune_get(20) == (128, 4)
+        assert jk.jk_tune_get(0) == dict(seg_max=2048, g_max=16, dig_kernel=2, eri_block=128)
+        # fields absent from an entry take their defaults
+        assert jk.jk_tune_get(20) == dict(seg_max=128, g_max=4, dig_kernel=1, eri_block=256)
         q = tmp_path / "other.json"
         q.write_text('{"arch": "gfx942", "entries": [{"class": 0, "seg_max": 64, "g_max": 4}]}')
         with pytest.raises(jk.JKError):
             jk.jk_tune_load(str(q))
-        assert jk.jk_tune_get(0) == (2048, 16)
+        assert jk.jk_tune_get(0)["seg_max"] == 2048
     finally:
-        for c, (sm, gm) in enumerate(old):
-            jk.jk_tune_set(c, sm, gm)
+        for c, t in enumerate(old):
+            jk.jk_tune_set(c, **t)

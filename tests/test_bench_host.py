@@ -66,9 +66,10 @@ def test_traffic_record_is_ignored_once_the_sources_change(tmp_path, monkeypatch
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
     rec = {"kernel": "eri_tile_2221", "source_sha256": bench.kernel_sources_sha256(),
            "hbm_bytes_per_launch": 123.0}
-    (tmp_path / "eri_tile_2221_medium312_traffic.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("eri_tile_2221") == 123.0
+    (tmp_path / "eri_tile_2221_large620_traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("eri_tile_2221", "large") == 123.0
+    assert bench.measured_traffic("eri_tile_2221", "medium") is None
     rec["source_sha256"] = "0" * 64
-    (tmp_path / "eri_tile_2221_medium312_traffic.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("eri_tile_2221") is None
-    assert bench.measured_traffic("digest_c_0000") is None
+    (tmp_path / "eri_tile_2221_large620_traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("eri_tile_2221", "large") is None
+    assert bench.measured_traffic("digest_c_0000", "large") is None

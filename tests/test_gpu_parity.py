@@ -545,6 +545,73 @@ def test_served_results_equal_alone(dev, precision):
     srv.close()
 
 
+def test_served_stream_resident_molecules_against_oracle(dev, capsys):
+    """The served stream over the 16 resident molecules (50-730 AO) in mixed
+    precision: a burst that the server folds into multi-request launches on
+    several slots, then a lone late request that replays a HIP graph.  Every
+    request equals the same request built alone; one request per molecule is
+    checked against the oracle: on molecules of at most 210 AO over whole
+    matrices (per density relative Frobenius), on the larger ones on sampled
+    blocks, whose error must stay within 1e-8 of the whole matrix's norm per
+    density (a necessary condition of the whole-matrix bar)."""
+    import torch
+    from paper_2607_05622_amd.serve import JKServer, Request
+
+    def note(msg):
+        with capsys.disabled():
+            print(f"[served] {msg}", flush=True)
+
+    mols = synth.config4_molecules()
+    bases = [m.basis for m in mols]
+    stream = synth.request_stream(24, 1.0)
+    reqs = []
+    for i, r in enumerate(stream):
+        mol = i % 16 if i < 16 else r["mol"]
+        nd = min(r["nd"], 16)
+        D = torch.tensor(synth.request_densities(mols[mol].meta["orbitals"], nd, r["seed"]), device=dev)
+        reqs.append(Request(i, 0.002 * i, mol, D))
+    # a lone request long after the burst: served by a graph replay
+    D = torch.tensor(synth.request_densities(mols[3].meta["orbitals"], 5, 4_100_000), device=dev)
+    reqs.append(Request(len(reqs), 8.0, 3, D))
+    t0 = time.perf_counter()
+    srv = JKServer(bases, n_slots=3, precision=jk.JK_MIXED, max_batch=6)
+    note(f"16 molecules resident ({min(b.nbf() for b in bases)}-{max(b.nbf() for b in bases)} AO) "
+         f"in {time.perf_counter() - t0:.1f} s")
+    launches = []
+    stats = srv.run(reqs, on_launch=lambda si, b: launches.append((si, len(b))))
+    note(f"{stats['requests']} requests served: mean batch {stats['mean_batch']:.2f}, "
+         f"graph fraction {stats['graph_fraction']:.2f}, slots used {sorted(set(s for s, _ in launches))}")
+    assert stats["requests"] == len(reqs)
+    assert max(n for _, n in launches) > 1 and len(set(s for s, _ in launches)) > 1
+    assert reqs[-1].graph
+    checked = set()
+    for r in reqs:
+        Ja, Ka = gpu_jk(bases[r.mol], r.D.cpu().numpy(), dev, precision=jk.JK_MIXED)
+        J, K = r.J.cpu().numpy(), r.K.cpu().numpy()
+        assert np.all(rel_frob(J, Ja) <= 1e-8) and np.all(rel_frob(K, Ka) <= 1e-8), r.index
+        if r.mol in checked and r.index != len(reqs) - 1:
+            continue
+        checked.add(r.mol)
+        if bases[r.mol].nbf() <= 210:
+            Jr, Kr = oracle.jk(bases[r.mol], r.D.cpu().numpy(), 1e-12)
+            fj, fk = rel_frob(J, Jr), rel_frob(K, Kr)
+        else:
+            blocks = sample_blocks(bases[r.mol], 40 + r.index, per_class=1, classes=((0, 0), (2, 1), (1, 2)))
+            refs = oracle.jk_blocks(bases[r.mol], r.D.cpu().numpy(), blocks, 1e-12)
+            fo = bases[r.mol].func_offsets()
+            dj2, dk2 = np.zeros(r.nd), np.zeros(r.nd)
+            for (a, c), (Jb, Kb) in zip(blocks, refs):
+                sl = (slice(None), slice(fo[a], fo[a + 1]), slice(fo[c], fo[c + 1]))
+                dj2 += np.sum((J[sl] - Jb) ** 2, axis=(1, 2))
+                dk2 += np.sum((K[sl] - Kb) ** 2, axis=(1, 2))
+            fj = np.sqrt(dj2 / np.sum(J ** 2, axis=(1, 2)))
+            fk = np.sqrt(dk2 / np.sum(K ** 2, axis=(1, 2)))
+        assert np.all(fj <= 1e-8) and np.all(fk <= 1e-8), (r.index, fj.max(), fk.max())
+    note(f"every request equals its own build; {len(checked)} molecules match the oracle on sampled blocks")
+    assert len(checked) == 16
+    srv.close()
+
+
 def test_served_low_budget_waits_but_completes(dev):
     from paper_2607_05622_amd.serve import JKServer
     bases = [synth.random_basis(1400 + i, 3 + i, 2) for i in range(2)]
@@ -582,5 +649,5 @@ def test_autotune_keeps_results(dev, tmp_path):
         jk.jk_tune_load(path)
     finally:
         h.close()
-        for c, (sm, gm) in enumerate(old):
-            jk.jk_tune_set(c, sm, gm)
+        for c, t in enumerate(old):
+            jk.jk_tune_set(c, **t)
