@@ -112,6 +112,23 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
 /* Device bytes one jk_build call with nd densities needs as workspace. */
 size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o);
 
+/* jk_build for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * same computation and arguments as jk_build (o->workspace and
+ * o->workspace_bytes are ignored), but the workspace is a static device
+ * buffer of the library of JK_NOALLOC_MAX_BYTES per device, held until the
+ * process ends; the call allocates nothing.  Its launch plan must exist:
+ * call jk_workspace_bytes(h, nd, o) once beforehand with the same nd and
+ * options (that call may allocate).  All calls on one device share the one
+ * buffer, so calls that overlap on a device (other streams, other threads)
+ * race and must not be issued; the buffer keeps the last call's contents,
+ * and each call clears what it accumulates into.  JK_EINVAL as jk_build and
+ * when no plan was prepared; JK_ENOMEM when jk_workspace_bytes(h, nd, o)
+ * exceeds JK_NOALLOC_MAX_BYTES. */
+#define JK_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int jk_build_noalloc(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
+                     const jk_build_opts* o);
+
 /* Builds for several molecules at once: nmol handles (same device), density
  * counts nd[i] and device pointers D[i], J[i], K[i] (host arrays of nmol
  * entries; matrices as in jk_build).  For every shell-quartet class and

@@ -26,6 +26,8 @@ namespace jk {
 
 using namespace jk;
 
+static_assert(kNoAllocScratchBytes == JK_NOALLOC_MAX_BYTES, "static workspace size");
+
 namespace {
 
 thread_local std::string g_err;
@@ -863,6 +865,8 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
 
     std::unique_ptr<jk_basis_s> h(new jk_basis_s());
     HIPC(hipGetDevice(&h->device));
+    // device address of the no-alloc entry point's static workspace (once per device)
+    HIPC(static_scratch_init());
     const int ns = d->nshells;
     h->natoms = d->natoms;
     h->ns = ns;
@@ -1203,6 +1207,35 @@ int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
     return JK_OK;
 }
 
+// The cached plan of a single-molecule build, or nullptr if none was made
+// yet for these options (never creates one).
+CachedPlan* find_plan(jk_basis_s* h, int nd, const jk_build_opts* o) {
+    const int mixed = o->precision == JK_MIXED;
+    int tgen;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tgen = g_tune_gen;
+    }
+    std::lock_guard<std::mutex> g(h->mu);
+    for (CachedPlan* cp : h->plans)
+        if (cp->nd == nd && cp->mixed == mixed && cp->want_j == o->want_j && cp->want_k == o->want_k &&
+            cp->gen == h->list_gen && cp->tgen == tgen)
+            return cp;
+    return nullptr;
+}
+
+// Whether the resident lists serve a build with tolerance tol and FP32
+// bound `bound` (bound < 0: any) without being rebuilt.
+bool lists_ready(jk_basis_s* h, double tol, double bound) {
+    std::lock_guard<std::mutex> g(h->mu);
+    int tg;
+    {
+        std::lock_guard<std::mutex> g2(g_tune_mu);
+        tg = g_tune_gen;
+    }
+    return h->list_tol >= 0 && h->list_tol <= tol && (bound < 0 || h->list_bound == bound) && h->tune_gen == tg;
+}
+
 // Pre- and post-stages of one molecule: D_cart, density screen, zeroed
 // accumulators; back-transform of J and K.
 hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_opts* o, char* base,
@@ -1334,6 +1367,52 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
         if (e == hipSuccess) e = e2;
     }
     if (e != hipSuccess) return fail(JK_EDEVICE, "jk_build: %s", hipGetErrorString(e));
+    {
+        std::lock_guard<std::mutex> g(h->mu);
+        for (int i = 0; i < 6; ++i) h->stats[i] = cp->wp.stats[i];
+    }
+    return JK_OK;
+}
+
+int jk_build_noalloc(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o) {
+    jk_build_opts def;
+    if (!o) {
+        jk_default_opts(&def);
+        o = &def;
+    }
+    if (!h) return fail(JK_EINVAL, "jk_build_noalloc: NULL handle");
+    if (nd < 1) return fail(JK_EINVAL, "jk_build_noalloc: nd=%d must be >= 1", nd);
+    int rc = check_opts("jk_build_noalloc", o);
+    if (rc) return rc;
+    if (!D) return fail(JK_EINVAL, "jk_build_noalloc: D is NULL");
+    if (o->want_j && !J) return fail(JK_EINVAL, "jk_build_noalloc: J is NULL but want_j is set");
+    if (o->want_k && !K) return fail(JK_EINVAL, "jk_build_noalloc: K is NULL but want_k is set");
+    DeviceGuard dg;
+    if ((rc = dg.ok(h->device))) return rc;
+    const int mixed = o->precision == JK_MIXED;
+    CachedPlan* cp = lists_ready(h, o->schwarz_tol, mixed ? o->fp32_bound : -1.0) ? find_plan(h, nd, o) : nullptr;
+    if (!cp)
+        return fail(JK_EINVAL,
+                    "jk_build_noalloc: no launch plan for nd=%d and these options; prepare it once with "
+                    "jk_workspace_bytes(h, nd, o), which may allocate",
+                    nd);
+    const MolSpace ms = mol_space(h, nd, o);
+    const size_t tb = tile_bytes_of(cp->wp);
+    const size_t total = ms.bytes + 2 * tb;
+    if (total > kNoAllocScratchBytes)
+        return fail(JK_ENOMEM,
+                    "jk_build_noalloc: the build needs %zu bytes of workspace, above the %zu of the static buffer",
+                    total, kNoAllocScratchBytes);
+    char* ws = static_cast<char*>(static_scratch(h->device));
+    if (!ws) return fail(JK_EDEVICE, "jk_build_noalloc: static workspace not set up on device %d", h->device);
+    hipStream_t s = static_cast<hipStream_t>(o->stream);
+    MolDesc md{};
+    hipError_t e = mol_pre(h, nd, D, o, ws, ms, md, s);
+    if (e == hipSuccess)
+        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, ws + ms.bytes + tb, o, h->d_boys,
+                     h->d_boys32, s, nullptr);
+    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, s);
+    if (e != hipSuccess) return fail(JK_EDEVICE, "jk_build_noalloc: %s", hipGetErrorString(e));
     {
         std::lock_guard<std::mutex> g(h->mu);
         for (int i = 0; i < 6; ++i) h->stats[i] = cp->wp.stats[i];

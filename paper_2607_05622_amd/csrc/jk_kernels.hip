@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "jk_internal.h"
 #include "jk_launch.h"
 
@@ -136,6 +138,42 @@ hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int
     hipLaunchKernelGGL(k_pair_dmax, dim3(blocks_for(static_cast<long long>(ns) * ns, 256)), dim3(256), 0, s, Dc,
                        nc, ndp, nd, shell_f0, shell_nf, ns, dmax);
     return hipGetLastError();
+}
+
+// ------------------------------------------- static workspace (no-alloc) ---
+
+// The workspace of jk_build_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  Host code never passes its name to a
+// kernel (on the host it is only a stand-in symbol); it uses the device
+// address hipGetSymbolAddress returns, looked up once per device with that
+// device current and kept here.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_addr[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+    return hipSuccess;
+}
+
+void* static_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_addr[dev];
 }
 
 hipError_t launch_zero(double* p, long long n, hipStream_t s) {

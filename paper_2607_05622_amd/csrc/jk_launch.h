@@ -127,4 +127,12 @@ hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int
                             int ns, double* dmax, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
 
+// Static workspace of jk_build_noalloc (bytes per device).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// Looks up and keeps the device address of the static workspace on the
+// current device (once per device; later calls return at once).
+hipError_t static_scratch_init();
+// The kept address on device dev, or nullptr before static_scratch_init ran there.
+void* static_scratch(int dev);
+
 }  // namespace jk

@@ -68,6 +68,8 @@ def load(path: str = LIB_PATH):
     lib.jk_nbf.restype = c_int
     lib.jk_build.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts)]
     lib.jk_build.restype = c_int
+    lib.jk_build_noalloc.argtypes = [vp, ctypes.c_int32, dp, dp, dp, ctypes.POINTER(jk_build_opts)]
+    lib.jk_build_noalloc.restype = c_int
     lib.jk_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(jk_build_opts)]
     lib.jk_workspace_bytes.restype = ctypes.c_size_t
     lib.jk_destroy.argtypes = [vp]
