@@ -33,7 +33,7 @@ __device__ __forceinline__ gptr<T> glob(T* p) {
 __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& mol0, int i) {
     if (!mols) return mol0;
     const gptr<const unsigned long long> w = (gptr<const unsigned long long>)(mols + i);
-    const gptr<const int> n = (gptr<const int>)(w + 7);
+    const gptr<const int> n = (gptr<const int>)(w + 9);
     MolDesc m;
     m.pairs = reinterpret_cast<const PairInfo*>(w[0]);
     m.prims = reinterpret_cast<const double*>(w[1]);
@@ -42,6 +42,8 @@ __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& 
     m.J = reinterpret_cast<double*>(w[4]);
     m.K = reinterpret_cast<double*>(w[5]);
     m.KT = reinterpret_cast<double*>(w[6]);
+    m.DS = reinterpret_cast<const double*>(w[7]);
+    m.ds_off = reinterpret_cast<const int*>(w[8]);
     m.ns = n[0];
     m.nc = n[1];
     m.nd = n[2];
@@ -264,18 +266,21 @@ __device__ __forceinline__ PrimPair load_prim(gptr<const v2d> pl, long long pslo
 }
 
 // Calls body(bra primitive pair, ket primitive pair) for every primitive
-// quartet, bra-major; a pair's records start in slot b0 (bra) or k0 (ket),
-// kPrimLane apart.  (Loading the next quartet's records ahead of the body
-// stopped paying once the ket records were laid out for coalesced loads.)
+// quartet, ket-major; a pair's records start in slot b0 (bra) or k0 (ket),
+// kPrimLane apart.  The lanes of a wavefront hold different ket pairs of
+// (mostly) one bra pair, so each ket record is loaded once per quartet and
+// the bra records, at one address across the wavefront, inside.  (Loading
+// the next quartet's records ahead of the body stopped paying once the ket
+// records were laid out for coalesced loads.)
 template <class Body>
 __device__ __forceinline__ void prim_loop(const MolDesc& m, int b0, int nb, int k0, int nk, Body body) {
     const gptr<const v2d> pl = glob(reinterpret_cast<const v2d*>(m.prims));
     const long long ps = m.pslots;
 #pragma unroll 1
-    for (int i = 0; i < nb; ++i) {
-        const PrimPair pp = load_prim(pl, ps, b0 + kPrimLane * i);
+    for (int j = 0; j < nk; ++j) {
+        const PrimPair qq = load_prim(pl, ps, k0 + kPrimLane * j);
 #pragma unroll 1
-        for (int j = 0; j < nk; ++j) body(pp, load_prim(pl, ps, k0 + kPrimLane * j));
+        for (int i = 0; i < nb; ++i) body(load_prim(pl, ps, b0 + kPrimLane * i), qq);
     }
 }
 

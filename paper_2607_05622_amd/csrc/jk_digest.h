@@ -7,6 +7,10 @@
 // and the same four with D^T into KT (the transposed contributions), so that
 // J = Jc + Jc^T and K = Kc + KTc^T hold for non-symmetric D (Eq. (jkbuild)).
 //
+// J reads D^S from records packed per shell pair (built once per call), so
+// the ket pairs of a bra block, visited in pair order, read neighbouring
+// records; the K updates read D itself.
+//
 // Each update is a contraction of the tile with a gather of the densities,
 // stacked along the MFMA N dimension: 16 densities (the D and D^T
 // contractions then run on separate waves), or 8 densities in columns 0-7
@@ -163,6 +167,7 @@ void k_digest_c(DigestArgs a) {
     __shared__ double sT[NF * QBP];
     __shared__ int sV[QB];
     __shared__ int sP[QB];
+    __shared__ int sO[QB];
 
     int p0 = 0, plen = 0, grp = 0;
     const DigItem* itp = dig_task(a, p0, plen, grp);
@@ -181,16 +186,17 @@ void k_digest_c(DigestArgs a) {
     const gptr<const int> posl = glob(it.pos) + it.blk0;
     const bool jrole = wave == 0;
 
+    // symmetrized densities of the lane's column (8-density groups: columns 0-7 only)
+    const bool jcol = G16 || c16 < 8;
+    const gptr<const double> dsx = glob(m.DS) + L.x;
     // J_cd's B operand, fixed for the task: D^S_ab at k-row ij = 4 t + r4
     double sab[KJ2];
+    {
+        const long long u0 = m.ds_off[sa * m.ns + sb];
 #pragma unroll
-    for (int t = 0; t < KJ2; ++t) {
-        const int ij = 4 * t + r4;
-        sab[t] = 0.0;
-        if (jrole && a.want_j && ij < NAB) {
-            const int i = ij / NB, j = ij - (ij / NB) * NB;
-            if constexpr (G16) sab[t] = L.d(fa + i, fb + j) + L.d(fb + j, fa + i);
-            else sab[t] = L.dk(fa + i, fb + j);
+        for (int t = 0; t < KJ2; ++t) {
+            const int ij = 4 * t + r4;
+            sab[t] = (jrole && a.want_j && ij < NAB && jcol) ? dsx[(u0 + ij) * L.ndp] : 0.0;
         }
     }
     // tile row of this lane's A operand in each accumulator tile of its role
@@ -224,6 +230,8 @@ void k_digest_c(DigestArgs a) {
         if (wave == 0 && lane < QB) {
             sV[lane] = lane < n ? kv.y >> 16 : fc;
             sP[lane] = lane < n ? posl[p + lane] : 0;
+            // first packed D^S unit of the quartet's ket pair (c, d)
+            sO[lane] = lane < n && a.want_j ? m.ds_off[(kv.x & 0xffff) * m.ns + (kv.x >> 16)] : 0;
         }
         // tile loads do not wait for the scan: positions past the run get weight 0
         for (int base = 0; base < NF * QB; base += static_cast<int>(blockDim.x)) {
@@ -248,16 +256,12 @@ void k_digest_c(DigestArgs a) {
                 // J_ab: contraction over (d in run, k, l)
                 for (int s = 0; s < nquad; ++s) {
                     const int qb = 4 * s + r4;
-                    const long long V0 = sV[qb];
-                    // the quad's B operands first, so their loads are in flight together
+                    const long long u = sO[qb];
+                    // the quad's B operands first, so their loads are in flight together:
+                    // the packed D^S record of the ket pair
                     double bv[NCD];
 #pragma unroll
-                    for (int k = 0; k < NC; ++k)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) {
-                            if constexpr (G16) bv[k * ND + l] = L.d(fc + k, V0 + l) + L.d(V0 + l, fc + k);
-                            else bv[k * ND + l] = L.dk(fc + k, V0 + l);
-                        }
+                    for (int v = 0; v < NCD; ++v) bv[v] = jcol ? dsx[(u + v) * L.ndp] : 0.0;
 #pragma unroll
                     for (int v = 0; v < NCD; ++v)
 #pragma unroll

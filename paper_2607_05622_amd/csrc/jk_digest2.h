@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     __shared__ double sTall[WPB][NF * QBP];
     __shared__ int sVall[WPB][QB];
     __shared__ int sPall[WPB][QB];
+    __shared__ int sOall[WPB][QB];
 
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     if (wave >= WPB) return;
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     double* sT = sTall[wave];
     int* sV = sVall[wave];
     int* sP = sPall[wave];
+    int* sO = sOall[wave];
     const DigItem it = *itp;
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
@@ -117,16 +119,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const gptr<const int> posl = glob(it.pos) + it.blk0;
     const bool wj = a.want_j, wk = a.want_k;
 
+    // symmetrized densities of the lane's column (8-density groups: columns 0-7 only)
+    const bool jcol = G16 || c16 < 8;
+    const gptr<const double> dsx = glob(m.DS) + L.x;
     // J_cd's B operand, fixed for the task: D^S_ab at k-row ij = 4 t + r4
     double sab[KJ2];
+    {
+        const long long u0 = wj ? m.ds_off[sa * m.ns + sb] : 0;
 #pragma unroll
-    for (int t = 0; t < KJ2; ++t) {
-        const int ij = 4 * t + r4;
-        sab[t] = 0.0;
-        if (wj && ij < NAB) {
-            const int i = ij / NB, j = ij - (ij / NB) * NB;
-            if constexpr (G16) sab[t] = L.d(fa + i, fb + j) + L.d(fb + j, fa + i);
-            else sab[t] = L.dk(fa + i, fb + j);
+        for (int t = 0; t < KJ2; ++t) {
+            const int ij = 4 * t + r4;
+            sab[t] = (wj && ij < NAB && jcol) ? dsx[(u0 + ij) * L.ndp] : 0.0;
         }
     }
     // tile row of the lane's A operand in each accumulator tile
@@ -165,6 +168,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (lane < QB) {
             sV[lane] = lane < n ? kv.y >> 16 : fc;
             sP[lane] = lane < n && wk && grp == 0 ? posl[p + lane] : 0;
+            // first packed D^S unit of the quartet's ket pair (c, d)
+            sO[lane] = lane < n && wj ? m.ds_off[(kv.x & 0xffff) * m.ns + (kv.x >> 16)] : 0;
         }
 #pragma unroll 4
         for (int base = 0; base < NF * QB; base += 64) {
@@ -189,15 +194,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             #pragma unroll 1
             for (int s = 0; s < nquad; ++s) {
                 const int qb = 4 * s + r4;
-                const long long V0 = sV[qb];
+                const long long u = sO[qb];
+                // the packed D^S record of the ket pair
                 double bv[NCD];
 #pragma unroll
-                for (int k = 0; k < NC; ++k)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) {
-                        if constexpr (G16) bv[k * ND + l] = L.d(fc + k, V0 + l) + L.d(V0 + l, fc + k);
-                        else bv[k * ND + l] = L.dk(fc + k, V0 + l);
-                    }
+                for (int v = 0; v < NCD; ++v) bv[v] = jcol ? dsx[(u + v) * L.ndp] : 0.0;
 #pragma unroll
                 for (int v = 0; v < NCD; ++v)
 #pragma unroll

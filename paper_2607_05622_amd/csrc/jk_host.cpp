@@ -192,6 +192,8 @@ struct jk_basis_s {
     UserMap* d_umap = nullptr;
     int* d_shell_f0 = nullptr;
     int* d_shell_nf = nullptr;
+    int* d_ds_off = nullptr;          // [ns][ns]: first packed unit of shell pair (c, d), c >= d
+    long long ds_units = 0;           // packed units over all shell pairs (sum of nc nd)
     // quartet lists for the current tolerance (older lists are retired, not
     // freed, because builds on other streams may still read them)
     std::mutex mu;
@@ -229,6 +231,7 @@ struct jk_basis_s {
         (void)hipFree(d_umap);
         (void)hipFree(d_shell_f0);
         (void)hipFree(d_shell_nf);
+        (void)hipFree(d_ds_off);
         for (auto& l : lists) {
             (void)hipFree(l.dev);
             (void)hipFree(l.dev_pos);
@@ -781,7 +784,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
 
 // Per-molecule workspace: densities and accumulators.
 struct MolSpace {
-    size_t off_D, off_J, off_K, off_KT, off_dmax, bytes;
+    size_t off_D, off_J, off_K, off_KT, off_dmax, off_DS, bytes;
 };
 
 inline size_t al256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -800,6 +803,8 @@ MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     if (o->want_k) off += al256(mat);
     m.off_dmax = off;
     off += al256(static_cast<size_t>(h->ns) * h->ns * sizeof(double));
+    m.off_DS = off;
+    if (o->want_j) off += al256(static_cast<size_t>(h->ds_units) * dens_stride(nd) * sizeof(double));
     m.bytes = off;
     return m;
 }
@@ -1064,6 +1069,17 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     if ((rc = upload(&h->d_umap, umap))) return rc;
     if ((rc = upload(&h->d_shell_f0, sf0))) return rc;
     if ((rc = upload(&h->d_shell_nf, h->ncart_int))) return rc;
+    {
+        // packed symmetrized-density records: shell pair (c, d), c >= d, in pair order
+        std::vector<int> off(static_cast<size_t>(ns) * ns, -1);
+        long long u = 0;
+        for (const PairInfo& P : h->pairs) {
+            off[static_cast<size_t>(P.sa) * ns + P.sb] = static_cast<int>(u);
+            u += static_cast<long long>(h->ncart_int[P.sa]) * h->ncart_int[P.sb];
+        }
+        h->ds_units = u;
+        if ((rc = upload(&h->d_ds_off, off))) return rc;
+    }
     if ((rc = compute_schwarz(h.get()))) return rc;
     HIPC(hipMemcpy(h->d_pairs, h->pairs.data(), h->pairs.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
     if ((rc = ensure_lists(h.get(), 1e-12, 1e-6))) return rc;
@@ -1247,8 +1263,12 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     double* dmax = reinterpret_cast<double*>(base + ms.off_dmax);
     const int ndp = dens_stride(nd);
     const long long mat = static_cast<long long>(h->nc) * h->nc * ndp;
+    double* DS = o->want_j ? reinterpret_cast<double*>(base + ms.off_DS) : nullptr;
     hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, ndp, Dc, s);
     if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
+    if (e == hipSuccess && DS)
+        e = launch_pair_ds(Dc, h->nc, ndp, nd, h->d_pairs, static_cast<int>(h->pairs.size()), h->d_shell_nf,
+                           h->d_ds_off, h->ns, DS, s);
     if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
     if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
     if (e == hipSuccess && KTc) e = launch_zero(KTc, mat, s);
@@ -1260,6 +1280,8 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     md.J = Jc;
     md.K = Kc;
     md.KT = KTc;
+    md.DS = DS;
+    md.ds_off = h->d_ds_off;
     md.ns = h->ns;
     md.nc = h->nc;
     md.nd = nd;

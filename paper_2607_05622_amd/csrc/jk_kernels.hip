@@ -70,6 +70,25 @@ __global__ void k_cart2sph(const double* __restrict__ Jc, const double* __restri
     }
 }
 
+// The symmetrized densities the Coulomb digestion reads, packed per shell
+// pair so that the ket pairs of a bra block, visited in pair order, read
+// neighbouring records: one thread per (pair, k, l), all densities.
+__global__ void k_pair_ds(const double* __restrict__ Dc, int nc, int ndp, int nd, const PairInfo* __restrict__ pairs,
+                          int npair, const int* __restrict__ shell_nf, const int* __restrict__ ds_off, int ns,
+                          double* __restrict__ DS) {
+    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int p = static_cast<int>(t / 36), kl = static_cast<int>(t - static_cast<long long>(p) * 36);
+    if (p >= npair) return;
+    const PairInfo P = pairs[p];
+    const int nb = shell_nf[P.sb];
+    if (kl >= shell_nf[P.sa] * nb) return;
+    const int k = kl / nb, l = kl - (kl / nb) * nb;
+    const double* a = Dc + (static_cast<long long>(P.fa + k) * nc + P.fb + l) * ndp;
+    const double* b = Dc + (static_cast<long long>(P.fb + l) * nc + P.fa + k) * ndp;
+    double* o = DS + (static_cast<long long>(ds_off[P.sa * ns + P.sb]) + kl) * ndp;
+    for (int x = 0; x < ndp; ++x) o[x] = x < nd ? a[x] + b[x] : 0.0;
+}
+
 // dmax[s][t] = max over the batch and both orientations of |Dc| in block (s, t).
 __global__ void k_pair_dmax(const double* __restrict__ Dc, int nc, int ndp, int nd, const int* __restrict__ shell_f0,
                             const int* __restrict__ shell_nf, int ns, double* __restrict__ dmax) {
@@ -130,6 +149,13 @@ hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc
     const long long n = static_cast<long long>(nf) * nf;
     hipLaunchKernelGGL(k_cart2sph, dim3(blocks_for(n, 256)), dim3(256), 0, s, Jc, Kc, KTc, nd, nf, umap, nc, ndp,
                        J, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_ds(const double* Dc, int nc, int ndp, int nd, const PairInfo* pairs, int npair,
+                          const int* shell_nf, const int* ds_off, int ns, double* DS, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_ds, dim3(blocks_for(static_cast<long long>(npair) * 36, 256)), dim3(256), 0, s, Dc, nc,
+                       ndp, nd, pairs, npair, shell_nf, ds_off, ns, DS);
     return hipGetLastError();
 }
 

@@ -35,12 +35,15 @@ struct MolDesc {
     double* J;              // Coulomb accumulator (J = Jc + Jc^T at the end)
     double* K;              // exchange, row contributions K[a][c]
     double* KT;             // exchange, transposed contributions (K += KT^T at the end)
+    const double* DS;       // D + D^T per shell pair (c >= d): [unit][ndp], unit = ds_off[c][d] + k ND + l
+    const int* ds_off;      // [ns][ns]: first unit of shell pair (c, d), c >= d in internal order
     int ns, nc, nd, ndp;
     int pslots, pad;        // entries per primitive-pair plane
 };
 // load_mol reads the fields at these offsets
-static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ns) == 56 &&
-                  __builtin_offsetof(MolDesc, pslots) == 72 && sizeof(MolDesc) == 80,
+static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ds_off) == 64 &&
+                  __builtin_offsetof(MolDesc, ns) == 72 && __builtin_offsetof(MolDesc, pslots) == 88 &&
+                  sizeof(MolDesc) == 96,
               "MolDesc layout");
 
 // A contiguous run of one molecule's class list whose tiles occupy
@@ -123,6 +126,10 @@ hipError_t launch_sph2cart(const double* D, int nd, int nf, const CartMap* cmap,
                            hipStream_t s);
 hipError_t launch_cart2sph(const double* Jc, const double* Kc, const double* KTc, int nd, int nf,
                            const UserMap* umap, int nc, int ndp, double* J, double* K, hipStream_t s);
+// DS[ds_off[c][d] + k ND + l][x] = Dc[fc + k][fd + l][x] + Dc[fd + l][fc + k][x] for every shell
+// pair c >= d (x < nd; zero up to ndp)
+hipError_t launch_pair_ds(const double* Dc, int nc, int ndp, int nd, const PairInfo* pairs, int npair,
+                          const int* shell_nf, const int* ds_off, int ns, double* DS, hipStream_t s);
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,
                             int ns, double* dmax, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
