@@ -77,7 +77,11 @@ typedef struct {
     double fp32_bound;      /* JK_MIXED: Q_ab Q_cd below this -> FP32, default 1e-6 */
     int32_t want_j;         /* default 1 */
     int32_t want_k;         /* default 1 */
-    int32_t symmetric_hint; /* reserved, must be 0 or 1; results never depend on it */
+    int32_t symmetric_hint; /* 0 (default) or 1: the caller promises D == D^T for every density;
+                               with more than 8 densities the exchange contractions with D^T
+                               (equal to those with D) are then skipped and K = Kc + Kc^T.
+                               For a non-symmetric D the K so built is that of (D + D^T)/2's
+                               D-half only: do not set it then.  J never depends on it. */
     void* stream;           /* hipStream_t for all work of the call; NULL = default stream */
     void* workspace;        /* optional device buffer of >= jk_workspace_bytes();
                                NULL: the library allocates stream-ordered memory */

@@ -33,7 +33,7 @@ hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
 template <int la, int lb, int lc, int ld, typename TT>
 hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16, int kernel) {
     constexpr int nf = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
-    if constexpr (dig2_class(la, lb, lc, ld, nf)) if (kernel == 2) {
+    if constexpr (dig2_class(la, lb, lc, ld, nf) && sizeof(TT) == 8) if (kernel == 2) {
         const dim3 grid(8 * ((a.nblocks / 8 + kDig2Waves - 1) / kDig2Waves));
         const dim3 block(64 * kDig2Waves);
         if (pass == 0) {
@@ -46,11 +46,13 @@ hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g
         return hipGetLastError();
     }
     const dim3 grid(a.nblocks);
+    // 16-density groups: the last wave takes the D^T contractions, left out
+    // when the densities are symmetric
     if (pass == 0) {
-        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(192), 0, s, a);
+        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(a.skip_t ? 128 : 192), 0, s, a);
         else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, dim3(128), 0, s, a);
     } else {
-        if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, dim3(128), 0, s, a);
+        if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, dim3(a.skip_t ? 64 : 128), 0, s, a);
         else hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, false>), grid, dim3(64), 0, s, a);
     }
     return hipGetLastError();

@@ -11,6 +11,12 @@
 // the ket pairs of a bra block, visited in pair order, read neighbouring
 // records; the K updates read D itself.
 //
+// The FP32 tier of mixed builds is digested in FP32: FP32 tiles against
+// FP32 copies of D and D^S on the FP32 matrix cores, each chunk's sums added
+// into FP64 accumulators, which are flushed into the FP64 J and K (the
+// paper's FP32 evaluation with FP64 accumulation, Sect. 3 mixed-precision
+// paragraph).
+//
 // Each update is a contraction of the tile with a gather of the densities,
 // stacked along the MFMA N dimension: 16 densities (the D and D^T
 // contractions then run on separate waves), or 8 densities in columns 0-7
@@ -40,6 +46,58 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
 }
 
 __device__ __forceinline__ void gadd(double* p, double v) { (void)__builtin_amdgcn_global_atomic_fadd_f64(glob(p), v); }
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Matrix-core step of the digestion in compute type R.  FP64: element e of
+// lane l holds output row 4 e + l / 16; FP32 (v_mfma_f32_16x16x4f32): row
+// 4 (l / 16) + e; both hold column l % 16 and take A[l % 16][l / 16],
+// B[l / 16][l % 16] (probed).
+template <typename R>
+struct DigMma;
+template <>
+struct DigMma<double> {
+    using V = v4d;
+    static __device__ __forceinline__ V step(double a, double b, V c) { return mfma_f64(a, b, c); }
+    static __device__ __forceinline__ int row(int e, int r4) { return 4 * e + r4; }
+    static __device__ __forceinline__ const double* dens(const MolDesc& m) { return m.D; }
+    static __device__ __forceinline__ const double* dsym(const MolDesc& m) { return m.DS; }
+};
+template <>
+struct DigMma<float> {
+    using V = v4f;
+    static __device__ __forceinline__ V step(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int e, int r4) { return 4 * r4 + e; }
+    static __device__ __forceinline__ const float* dens(const MolDesc& m) { return m.Df; }
+    static __device__ __forceinline__ const float* dsym(const MolDesc& m) { return m.DSf; }
+};
+
+// Accumulator tile of a sum that spans chunks: FP64 runs accumulate in the
+// matrix-core registers directly; FP32 runs keep each chunk's sum in FP32
+// and add it into an FP64 copy at the end of the chunk (fold).
+template <typename R>
+struct DigAcc {
+    typename DigMma<R>::V a;
+    v4d s;   // FP64 sum of the folded chunks (unused for R = double)
+    __device__ __forceinline__ void zero() {
+        a = typename DigMma<R>::V{0, 0, 0, 0};
+        if constexpr (sizeof(R) == 4) s = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    __device__ __forceinline__ void fold() {
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s[e] += static_cast<double>(a[e]);
+            a = typename DigMma<R>::V{0, 0, 0, 0};
+        }
+    }
+    // the FP64 value of element e (after fold for R = float)
+    __device__ __forceinline__ double get(int e) const {
+        if constexpr (sizeof(R) == 4) return s[e];
+        else return a[e];
+    }
+};
 
 // Workgroup barrier that orders LDS only: the waves' atomics and stores to
 // device memory stay in flight across it (nothing in the workgroup reads
@@ -95,20 +153,21 @@ struct DigShape {
 // Density access of one lane.  The lane's MFMA column is density x; its K
 // contractions read D[F][V] (tr = false) or D[V][F] (tr = true) for a fixed
 // bra-side function F and a ket-side function V.
+template <typename R = double>
 struct DigLane {
     int x;
     bool tr;
     long long sRow, ndp, sF, sV;
-    gptr<const double> Dx;
+    gptr<const R> Dx;
     __device__ DigLane(const MolDesc& m, int x_, bool tr_) : x(x_), tr(tr_) {
         ndp = m.ndp;
         sRow = static_cast<long long>(m.nc) * ndp;
         sF = tr ? ndp : sRow;
         sV = tr ? sRow : ndp;
-        Dx = glob(m.D) + x;
+        Dx = glob(DigMma<R>::dens(m)) + x;
     }
-    __device__ __forceinline__ double d(long long r, long long c) const { return Dx[r * sRow + c * ndp]; }
-    __device__ __forceinline__ double dk(long long F, long long V) const { return Dx[F * sF + V * sV]; }
+    __device__ __forceinline__ R d(long long r, long long c) const { return Dx[r * sRow + c * ndp]; }
+    __device__ __forceinline__ R dk(long long F, long long V) const { return Dx[F * sF + V * sV]; }
 };
 
 // Fold weight of a canonical quartet from its shells: 1/2 for a = b, for
@@ -120,19 +179,20 @@ __device__ __forceinline__ double fold_weight(int sa, int sb, int sc, int sd) {
 // Adds a finished K accumulator tile into K (D contraction) or KT (D^T
 // contraction) and clears it; rowmap turns an output row into its (row,
 // column) function.
-template <int NROW, class RowMap>
-__device__ __forceinline__ void dig_flush_k(const MolDesc& m, const DigLane& L, int r4, v4d& acc, int mt,
+template <int NROW, typename R, class RowMap>
+__device__ __forceinline__ void dig_flush_k(const MolDesc& m, const DigLane<R>& L, int r4, DigAcc<R>& acc, int mt,
                                             RowMap rowmap) {
+    acc.fold();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int mo = mt * 16 + 4 * r + r4;
+        const int mo = mt * 16 + DigMma<R>::row(r, r4);
         if (mo < NROW && L.x < m.nd) {
             long long row, col;
             rowmap(mo, row, col);
-            gadd((L.tr ? m.KT : m.K) + (row * m.nc + col) * L.ndp + L.x, acc[r]);
+            gadd((L.tr ? m.KT : m.K) + (row * m.nc + col) * L.ndp + L.x, acc.get(r));
         }
     }
-    acc = v4d{0.0, 0.0, 0.0, 0.0};
+    acc.zero();
 }
 
 // Scan of the next chunk, done identically by every wave: up to QB
@@ -164,7 +224,9 @@ void k_digest_c(DigestArgs a) {
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NAB = S::NAB, NCD = S::NCD;
     constexpr int QB = S::QB, QBP = S::QBP;
     constexpr int MJ = S::MJ, M2 = S::M2, KJ2 = S::KJ2, M3 = S::M3, M4 = S::M4, NACC = S::NACC_C;
-    __shared__ double sT[NF * QBP];
+    using R = TT;               // compute type: FP64 tier in FP64, FP32 tier in FP32
+    using MM = DigMma<R>;
+    __shared__ R sT[NF * QBP];
     __shared__ int sV[QB];
     __shared__ int sP[QB];
     __shared__ int sO[QB];
@@ -176,7 +238,7 @@ void k_digest_c(DigestArgs a) {
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
-    const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 2 : c16 >= 8);
+    const DigLane<R> L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 2 : c16 >= 8);
     const long long nc = m.nc;
     const PairInfo& P = m.pairs[it.bra];
     const int fa = P.fa, fb = P.fb, sa = P.sa, sb = P.sb;
@@ -188,15 +250,15 @@ void k_digest_c(DigestArgs a) {
 
     // symmetrized densities of the lane's column (8-density groups: columns 0-7 only)
     const bool jcol = G16 || c16 < 8;
-    const gptr<const double> dsx = glob(m.DS) + L.x;
+    const gptr<const R> dsx = glob(MM::dsym(m)) + L.x;
     // J_cd's B operand, fixed for the task: D^S_ab at k-row ij = 4 t + r4
-    double sab[KJ2];
+    R sab[KJ2];
     {
         const long long u0 = m.ds_off[sa * m.ns + sb];
 #pragma unroll
         for (int t = 0; t < KJ2; ++t) {
             const int ij = 4 * t + r4;
-            sab[t] = (jrole && a.want_j && ij < NAB && jcol) ? dsx[(u0 + ij) * L.ndp] : 0.0;
+            sab[t] = (jrole && a.want_j && ij < NAB && jcol) ? dsx[(u0 + ij) * L.ndp] : R(0);
         }
     }
     // tile row of this lane's A operand in each accumulator tile of its role
@@ -215,9 +277,9 @@ void k_digest_c(DigestArgs a) {
             if (r < NB * NC) frow[t] = (r / NC) * NCD + (r % NC) * ND;
         }
     }
-    v4d acc[NACC];
+    DigAcc<R> acc[NACC];
 #pragma unroll
-    for (int t = 0; t < NACC; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NACC; ++t) acc[t].zero();
 
     const int pend = p0 + plen;
     for (int p = p0; p < pend;) {
@@ -226,7 +288,7 @@ void k_digest_c(DigestArgs a) {
         const int n = dig_chunk<QB>(kin, p, pend, lane, 0, kv, more);
         const int fc = __shfl(kv.y & 0xffff, 0);
         // fold weight of the lane's quartet (0 past the chunk), applied to the staged tile
-        const double wl = lane < n ? fold_weight(sa, sb, kv.x & 0xffff, kv.x >> 16) : 0.0;
+        const R wl = lane < n ? static_cast<R>(fold_weight(sa, sb, kv.x & 0xffff, kv.x >> 16)) : R(0);
         if (wave == 0 && lane < QB) {
             sV[lane] = lane < n ? kv.y >> 16 : fc;
             sP[lane] = lane < n ? posl[p + lane] : 0;
@@ -237,9 +299,9 @@ void k_digest_c(DigestArgs a) {
         for (int base = 0; base < NF * QB; base += static_cast<int>(blockDim.x)) {
             const int idx = base + static_cast<int>(threadIdx.x);
             const int f = idx / QB, qb = idx - (idx / QB) * QB;
-            double t = 0.0;
-            if (idx < NF * QB && p + qb < pend) t = static_cast<double>(tile[f * nq + qrel + p + qb]);
-            const double w = __shfl(wl, qb);
+            R t = R(0);
+            if (idx < NF * QB && p + qb < pend) t = tile[f * nq + qrel + p + qb];
+            const R w = __shfl(wl, qb);
             if (idx < NF * QB) sT[f * QBP + qb] = w * t;
         }
         lds_barrier();
@@ -259,31 +321,33 @@ void k_digest_c(DigestArgs a) {
                     const long long u = sO[qb];
                     // the quad's B operands first, so their loads are in flight together:
                     // the packed D^S record of the ket pair
-                    double bv[NCD];
+                    R bv[NCD];
 #pragma unroll
-                    for (int v = 0; v < NCD; ++v) bv[v] = jcol ? dsx[(u + v) * L.ndp] : 0.0;
+                    for (int v = 0; v < NCD; ++v) bv[v] = jcol ? dsx[(u + v) * L.ndp] : R(0);
 #pragma unroll
                     for (int v = 0; v < NCD; ++v)
 #pragma unroll
                         for (int t = 0; t < MJ; ++t)
-                            acc[t] = mfma_f64(sT[(frow[t] + v) * QBP + qb], bv[v], acc[t]);
+                            acc[t].a = MM::step(sT[(frow[t] + v) * QBP + qb], bv[v], acc[t].a);
                 }
+#pragma unroll
+                for (int t = 0; t < MJ; ++t) acc[t].fold();
                 // J_cd: one output row per (quartet, k, l), contraction over (i, j)
                 for (int mt = 0; mt < M2; ++mt) {
                     if (mt * 16 >= n * NCD) break;
                     const int r = mt * 16 + c16;
                     const int qa = r < QB * NCD ? r / NCD : 0, va = r < QB * NCD ? r - (r / NCD) * NCD : 0;
-                    v4d cd = {0.0, 0.0, 0.0, 0.0};
+                    typename MM::V cd = {0, 0, 0, 0};
 #pragma unroll
                     for (int t = 0; t < KJ2; ++t) {
                         const int ij = 4 * t + r4 < NAB ? 4 * t + r4 : NAB - 1;
-                        cd = mfma_f64(sT[(ij * NCD + va) * QBP + qa], sab[t], cd);
+                        cd = MM::step(sT[(ij * NCD + va) * QBP + qa], sab[t], cd);
                     }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        double v = cd[e];
+                        double v = static_cast<double>(cd[e]);
                         if constexpr (!G16) v += __shfl_xor(v, 8);
-                        const int mo = mt * 16 + 4 * e + r4;
+                        const int mo = mt * 16 + MM::row(e, r4);
                         const int qo = mo / NCD, vo = mo - (mo / NCD) * NCD;
                         if (qo < n && L.x < m.nd && !L.tr) {
                             const int k = vo / ND, l = vo - (vo / ND) * ND;
@@ -297,7 +361,7 @@ void k_digest_c(DigestArgs a) {
                 const int qb = 4 * s + r4;
                 const long long V0 = sV[qb];
                 // the quad's B operands first: D_bd for K_ac, D_ad for K_bc
-                double b3[NB * ND], b4[NA * ND];
+                R b3[NB * ND], b4[NA * ND];
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
 #pragma unroll
@@ -313,7 +377,7 @@ void k_digest_c(DigestArgs a) {
                     for (int l = 0; l < ND; ++l)
 #pragma unroll
                         for (int t = 0; t < M3; ++t)
-                            acc[t] = mfma_f64(sT[(frow[t] + j * NCD + l) * QBP + qb], b3[j * ND + l], acc[t]);
+                            acc[t].a = MM::step(sT[(frow[t] + j * NCD + l) * QBP + qb], b3[j * ND + l], acc[t].a);
                 // K_bc: contraction over (i, l)
 #pragma unroll
                 for (int i = 0; i < NA; ++i)
@@ -321,8 +385,10 @@ void k_digest_c(DigestArgs a) {
                     for (int l = 0; l < ND; ++l)
 #pragma unroll
                         for (int t = M3; t < M3 + M4; ++t)
-                            acc[t] = mfma_f64(sT[(frow[t] + i * NB * NCD + l) * QBP + qb], b4[i * ND + l], acc[t]);
+                            acc[t].a = MM::step(sT[(frow[t] + i * NB * NCD + l) * QBP + qb], b4[i * ND + l], acc[t].a);
             }
+#pragma unroll
+            for (int t = 0; t < M3 + M4; ++t) acc[t].fold();
             if (!more) {
 #pragma unroll
                 for (int t = 0; t < M3; ++t)
@@ -346,9 +412,9 @@ void k_digest_c(DigestArgs a) {
         for (int t = 0; t < MJ; ++t)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                double v = acc[t][e];
+                double v = acc[t].get(e);
                 if constexpr (!G16) v += __shfl_xor(v, 8);
-                const int mo = t * 16 + 4 * e + r4;
+                const int mo = t * 16 + MM::row(e, r4);
                 if (mo < NAB && L.x < m.nd && !L.tr) {
                     const int i = mo / NB, j = mo - (mo / NB) * NB;
                     gadd(m.J + ((fa + i) * nc + fb + j) * L.ndp + L.x, v);
@@ -366,7 +432,9 @@ void k_digest_d(DigestArgs a) {
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NCD = S::NCD;
     constexpr int QB = S::QB_D, QBP = S::QBP_D;
     constexpr int M5 = S::M5, M6 = S::M6, NACC = S::NACC_D;
-    __shared__ double sT[NF * QBP];
+    using R = TT;
+    using MM = DigMma<R>;
+    __shared__ R sT[NF * QBP];
     __shared__ int sV[QB];
 
     int p0 = 0, plen = 0, grp = 0;
@@ -376,7 +444,7 @@ void k_digest_d(DigestArgs a) {
     const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
-    const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 1 : c16 >= 8);
+    const DigLane<R> L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 1 : c16 >= 8);
     const PairInfo& P = m.pairs[it.bra];
     const int fa = P.fa, fb = P.fb;
     const gptr<const TT> cp = glob(static_cast<const TT*>(a.dcopy)) + it.tile_off;
@@ -395,9 +463,9 @@ void k_digest_d(DigestArgs a) {
             if (r < NB * ND) frow[t] = (r / ND) * NCD + r % ND;
         }
     }
-    v4d acc[NACC];
+    DigAcc<R> acc[NACC];
 #pragma unroll
-    for (int t = 0; t < NACC; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NACC; ++t) acc[t].zero();
 
     const int pend = p0 + plen;
     for (int p = p0; p < pend;) {
@@ -409,9 +477,9 @@ void k_digest_d(DigestArgs a) {
         for (int base = 0; base < NF * QB; base += static_cast<int>(blockDim.x)) {
             const int idx = base + static_cast<int>(threadIdx.x);
             const int qb = idx / NF, f = idx - (idx / NF) * NF;
-            double t = 0.0;
-            if (idx < NF * QB && p + qb < pend) t = static_cast<double>(cp[(qrel + p + qb) * NF + f]);
-            if (idx < NF * QB) sT[f * QBP + qb] = qb < n ? t : 0.0;
+            R t = R(0);
+            if (idx < NF * QB && p + qb < pend) t = cp[(qrel + p + qb) * NF + f];
+            if (idx < NF * QB) sT[f * QBP + qb] = qb < n ? t : R(0);
         }
         lds_barrier();
         const int nquad = (n + 3) >> 2;
@@ -419,7 +487,7 @@ void k_digest_d(DigestArgs a) {
             const int qb = 4 * s + r4;
             const long long V0 = sV[qb];
             // the quad's B operands first: D_bc for K_ad, D_ac for K_bd
-            double b5[NB * NC], b6[NA * NC];
+            R b5[NB * NC], b6[NA * NC];
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
@@ -435,7 +503,7 @@ void k_digest_d(DigestArgs a) {
                 for (int k = 0; k < NC; ++k)
 #pragma unroll
                     for (int t = 0; t < M5; ++t)
-                        acc[t] = mfma_f64(sT[(frow[t] + j * NCD + k * ND) * QBP + qb], b5[j * NC + k], acc[t]);
+                        acc[t].a = MM::step(sT[(frow[t] + j * NCD + k * ND) * QBP + qb], b5[j * NC + k], acc[t].a);
             // K_bd: contraction over (i, k)
 #pragma unroll
             for (int i = 0; i < NA; ++i)
@@ -443,8 +511,10 @@ void k_digest_d(DigestArgs a) {
                 for (int k = 0; k < NC; ++k)
 #pragma unroll
                     for (int t = M5; t < M5 + M6; ++t)
-                        acc[t] = mfma_f64(sT[(frow[t] + i * NB * NCD + k * ND) * QBP + qb], b6[i * NC + k], acc[t]);
+                        acc[t].a = MM::step(sT[(frow[t] + i * NB * NCD + k * ND) * QBP + qb], b6[i * NC + k], acc[t].a);
         }
+#pragma unroll
+        for (int t = 0; t < NACC; ++t) acc[t].fold();
         if (!more) {
 #pragma unroll
             for (int t = 0; t < M5; ++t)

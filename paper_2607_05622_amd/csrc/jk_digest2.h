@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
     // the lane's density column; tr: its column holds D^T (8-density groups only)
-    const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? false : c16 >= 8);
+    const DigLane<double> L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? false : c16 >= 8);
     const bool live = L.x < m.nd;
     const long long nc = m.nc;
     const PairInfo& P = m.pairs[it.bra];
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const long long nq = it.chunk_n, qrel = it.blk0 - it.chunk_q0;
     const gptr<const long long> kin = glob(reinterpret_cast<const long long*>(it.kin)) + it.blk0;
     const gptr<const int> posl = glob(it.pos) + it.blk0;
-    const bool wj = a.want_j, wk = a.want_k;
+    const bool wj = a.want_j, wk = a.want_k, skipT = a.skip_t != 0;
 
     // symmetrized densities of the lane's column (8-density groups: columns 0-7 only)
     const bool jcol = G16 || c16 < 8;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         for (int t = 0; t < M3; ++t) {
                             const double av = sT[(fk[t] + j * NCD + l) * QBP + qb];
                             accK[t] = mfma_f64(av, b3[j], accK[t]);
-                            if constexpr (G16) accT[t] = mfma_f64(av, t3[j], accT[t]);
+                            if (G16 && !skipT) accT[t] = mfma_f64(av, t3[j], accT[t]);
                         }
 #pragma unroll
                     for (int i = 0; i < NA; ++i)
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         for (int t = M3; t < NK; ++t) {
                             const double av = sT[(fk[t] + i * NB * NCD + l) * QBP + qb];
                             accK[t] = mfma_f64(av, b4[i], accK[t]);
-                            if constexpr (G16) accT[t] = mfma_f64(av, t4[i], accT[t]);
+                            if (G16 && !skipT) accT[t] = mfma_f64(av, t4[i], accT[t]);
                         }
                 }
             }
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int t = 0; t < M3; ++t) dig2_flush<NA * NC>(kd, nc, L.ndp, L.x, live, r4, accK[t], t, mac);
 #pragma unroll
                 for (int t = M3; t < NK; ++t) dig2_flush<NB * NC>(kd, nc, L.ndp, L.x, live, r4, accK[t], t - M3, mbc);
-                if constexpr (G16) {
+                if (G16 && !skipT) {
 #pragma unroll
                     for (int t = 0; t < M3; ++t) dig2_flush<NA * NC>(m.KT, nc, L.ndp, L.x, live, r4, accT[t], t, mac);
 #pragma unroll
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const DigItem it = *itp;
     const int c16 = lane & 15, r4 = lane >> 4;
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
-    const DigLane L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? false : c16 >= 8);
+    const DigLane<double> L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? false : c16 >= 8);
     const bool live = L.x < m.nd;
     const long long nc = m.nc;
     const PairInfo& P = m.pairs[it.bra];
@@ -340,6 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const gptr<const TT> cp = glob(static_cast<const TT*>(a.dcopy)) + it.tile_off;
     const long long qrel = it.blk0 - it.chunk_q0;
     const gptr<const long long> kin = glob(reinterpret_cast<const long long*>(it.kin)) + it.blk0;
+    const bool skipT = a.skip_t != 0;
 
     int fk[NK];
 #pragma unroll
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     for (int t = 0; t < M5; ++t) {
                         const double av = sT[(fk[t] + j * NCD + k * ND) * QBP + qb];
                         accK[t] = mfma_f64(av, b5[j], accK[t]);
-                        if constexpr (G16) accT[t] = mfma_f64(av, t5[j], accT[t]);
+                        if (G16 && !skipT) accT[t] = mfma_f64(av, t5[j], accT[t]);
                     }
 #pragma unroll
                 for (int i = 0; i < NA; ++i)
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     for (int t = M5; t < NK; ++t) {
                         const double av = sT[(fk[t] + i * NB * NCD + k * ND) * QBP + qb];
                         accK[t] = mfma_f64(av, b6[i], accK[t]);
-                        if constexpr (G16) accT[t] = mfma_f64(av, t6[i], accT[t]);
+                        if (G16 && !skipT) accT[t] = mfma_f64(av, t6[i], accT[t]);
                     }
             }
         }
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int t = 0; t < M5; ++t) dig2_flush<NA * ND>(kd, nc, L.ndp, L.x, live, r4, accK[t], t, mad);
 #pragma unroll
             for (int t = M5; t < NK; ++t) dig2_flush<NB * ND>(kd, nc, L.ndp, L.x, live, r4, accK[t], t - M5, mbd);
-            if constexpr (G16) {
+            if (G16 && !skipT) {
 #pragma unroll
                 for (int t = 0; t < M5; ++t) dig2_flush<NA * ND>(m.KT, nc, L.ndp, L.x, live, r4, accT[t], t, mad);
 #pragma unroll

@@ -60,6 +60,11 @@ constexpr double kPrimPairTol = 1e-18;
 // high angular momentum class holds a few hundred thousand quartets, many
 // waves per SIMD at its one-wave occupancy.
 constexpr long long kTileCapElems = 256ll << 20;
+// Launch lanes of a build: consecutive class/tier launches alternate between
+// the caller's stream and a helper stream of the handle, each lane with its
+// own integral work and scratch buffers, so one class's integrals overlap
+// another's digestion and the launches' ramp-ups and tails overlap.
+constexpr int kLanes = 2;
 
 double dfact(int n) {
     double r = 1.0;
@@ -116,7 +121,7 @@ int class_nf(int cls) { return kClassCost[cls].nfunc; }
 // most 8 densities), the digestion kernel (1: workgroup-shared chunks, 2:
 // wave-private tasks) and the quartets per integral workgroup.
 struct Tune {
-    int seg_max = 128;
+    int seg_max = 256;
     int g_max = 16;
     int dig_kernel = 1;
     int eri_block = 256;
@@ -193,6 +198,7 @@ struct jk_basis_s {
     int* d_shell_f0 = nullptr;
     int* d_shell_nf = nullptr;
     int* d_ds_off = nullptr;          // [ns][ns]: first packed unit of shell pair (c, d), c >= d
+    hipStream_t aux = nullptr;        // helper stream of the second launch lane (default priority)
     long long ds_units = 0;           // packed units over all shell pairs (sum of nc nd)
     // quartet lists for the current tolerance (older lists are retired, not
     // freed, because builds on other streams may still read them)
@@ -232,6 +238,7 @@ struct jk_basis_s {
         (void)hipFree(d_shell_f0);
         (void)hipFree(d_shell_nf);
         (void)hipFree(d_ds_off);
+        if (aux) (void)hipStreamDestroy(aux);
         for (auto& l : lists) {
             (void)hipFree(l.dev);
             (void)hipFree(l.dev_pos);
@@ -622,6 +629,7 @@ struct MolRun {
 };
 
 struct WorkPlan {
+    bool skip_t = false;             // symmetric densities: KT contractions skipped (K = Kc + Kc^T)
     std::vector<EriItem> eri;
     std::vector<DigItem> dig[2];
     std::vector<LaunchRec> launches;
@@ -641,10 +649,13 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
     const bool mixed = o->precision == JK_MIXED;
     bool all16 = true;
     for (const MolRun& r : mols) all16 = all16 && dens_stride(r.nd) % 16 == 0;
+    // symmetric densities: with 16-density groups the D^T contractions give
+    // the same sums as the D ones, so they are skipped and K = Kc + Kc^T
+    wp.skip_t = o->symmetric_hint && o->want_k && all16;
     for (int c = 0; c < kNumClass; ++c) {
         const int NF = class_nf(c);
         const Tune tn = tune_of(c);
-        const int g16 = all16 && tn.g_max >= 16;
+        const int g16 = all16 && (wp.skip_t || tn.g_max >= 16);
         const int G = g16 ? 16 : 8;
         for (int tier = 0; tier < (mixed ? 2 : 1); ++tier) {
             const int fp32 = mixed && tier == 1;
@@ -784,7 +795,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
 
 // Per-molecule workspace: densities and accumulators.
 struct MolSpace {
-    size_t off_D, off_J, off_K, off_KT, off_dmax, off_DS, bytes;
+    size_t off_D, off_J, off_K, off_KT, off_dmax, off_DS, off_Df, off_DSf, bytes;
 };
 
 inline size_t al256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -804,14 +815,21 @@ MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     m.off_dmax = off;
     off += al256(static_cast<size_t>(h->ns) * h->ns * sizeof(double));
     m.off_DS = off;
-    if (o->want_j) off += al256(static_cast<size_t>(h->ds_units) * dens_stride(nd) * sizeof(double));
+    const size_t ds = static_cast<size_t>(h->ds_units) * dens_stride(nd);
+    if (o->want_j) off += al256(ds * sizeof(double));
+    // FP32 copies for the FP32 tier of mixed builds
+    const bool mixed = o->precision == JK_MIXED;
+    m.off_Df = off;
+    if (mixed && o->want_k) off += al256(mat / 2);
+    m.off_DSf = off;
+    if (mixed && o->want_j) off += al256(ds * sizeof(float));
     m.bytes = off;
     return m;
 }
 
 // A cached plan of a single-molecule build, with its items on the device.
 struct CachedPlan {
-    int nd, mixed, want_j, want_k, gen, tgen;
+    int nd, mixed, want_j, want_k, sym, gen, tgen;
     WorkPlan wp;
     EriItem* d_eri = nullptr;
     DigItem* d_dig[2] = {nullptr, nullptr};
@@ -872,6 +890,7 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out) {
     HIPC(hipGetDevice(&h->device));
     // device address of the no-alloc entry point's static workspace (once per device)
     HIPC(static_scratch_init());
+    HIPC(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
     const int ns = d->nshells;
     h->natoms = d->natoms;
     h->ns = ns;
@@ -1122,11 +1141,33 @@ namespace {
 
 // Launch every class/tier of a plan on stream s.  prof: handle that records
 // per-kernel events when profiling is on (single-molecule builds).
+// Launch every class/tier of a plan: launch i runs on lane i % kLanes (lane 0
+// the caller's stream s, lane 1 the helper stream aux, forked from and joined
+// back into s) with that lane's integral work buffer and scratch, each tb
+// bytes at work + 2 lane tb and work + (2 lane + 1) tb.
 hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_dig[2], const MolDesc& mol0,
-                    const MolDesc* d_mols, void* tiles, void* scratch, const jk_build_opts* o, const double* boys,
-                    const float* boys32, hipStream_t s, jk_basis_s* prof) {
+                    const MolDesc* d_mols, char* work, size_t tb, const jk_build_opts* o, const double* boys,
+                    const float* boys32, hipStream_t s, hipStream_t aux, jk_basis_s* prof) {
     hipError_t e = hipSuccess;
-    for (const LaunchRec& L : wp.launches) {
+    const int lanes = (aux && wp.launches.size() > 1) ? kLanes : 1;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (lanes > 1) {
+        e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux, fork, 0);
+        if (e != hipSuccess) {
+            if (fork) (void)hipEventDestroy(fork);
+            if (join) (void)hipEventDestroy(join);
+            return e;
+        }
+    }
+    for (size_t li = 0; li < wp.launches.size() && e == hipSuccess; ++li) {
+        const LaunchRec& L = wp.launches[li];
+        const int lane = static_cast<int>(li % lanes);
+        const hipStream_t ls = lane ? aux : s;
+        void* const tiles = work + 2 * lane * tb;
+        void* const scratch = work + (2 * lane + 1) * tb;
         EriTileArgs ea{};
         ea.items = d_eri + L.eri0;
         ea.nitems = L.neri;
@@ -1150,6 +1191,7 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
             da[ps].dcopy = scratch;
             da[ps].want_j = o->want_j;
             da[ps].want_k = o->want_k;
+            da[ps].skip_t = wp.skip_t ? 1 : 0;
             da[ps].nblocks = L.ndig[ps] > 0 ? L.dig_blocks[ps] : 0;
         }
         const bool timed = prof && prof->profiling;
@@ -1157,16 +1199,16 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
         if (timed) {
             for (auto& x : ev)
                 if (e == hipSuccess) e = hipEventCreate(&x);
-            if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-            if (e != hipSuccess) return e;
+            if (e == hipSuccess) e = hipEventRecord(ev[0], ls);
+            if (e != hipSuccess) break;
         }
-        e = launch_eri_tile(L.cls, ea, s, L.fp32);
-        if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
-        if (e == hipSuccess) e = launch_digest(L.cls, da[0], s, L.fp32, 0, L.g16, L.dig_kernel);
-        if (e == hipSuccess && timed) e = hipEventRecord(ev[2], s);
-        if (e == hipSuccess) e = launch_digest(L.cls, da[1], s, L.fp32, 1, L.g16, L.dig_kernel);
-        if (e == hipSuccess && timed) e = hipEventRecord(ev[3], s);
-        if (e != hipSuccess) return e;
+        e = launch_eri_tile(L.cls, ea, ls, L.fp32);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[1], ls);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[0], ls, L.fp32, 0, L.g16, L.dig_kernel);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[2], ls);
+        if (e == hipSuccess) e = launch_digest(L.cls, da[1], ls, L.fp32, 1, L.g16, L.dig_kernel);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[3], ls);
+        if (e != hipSuccess) break;
         if (timed) {
             std::lock_guard<std::mutex> g(prof->mu);
             prof->prof.push_back({0 + 2 * L.fp32, L.cls, ev[0], ev[1], L.eri_flops, L.quartets, L.tile_bytes});
@@ -1176,6 +1218,15 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
             else
                 (void)hipEventDestroy(ev[3]);
         }
+    }
+    if (lanes > 1) {
+        // join lane 1 back into s whatever happened, so nothing after the
+        // build on s (the back-transform, a workspace free) runs before it
+        hipError_t e2 = hipEventRecord(join, aux);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(s, join, 0);
+        if (e == hipSuccess) e = e2;
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
     }
     return e;
 }
@@ -1199,7 +1250,7 @@ int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
     std::lock_guard<std::mutex> g(h->mu);
     for (CachedPlan* cp : h->plans)
         if (cp->nd == nd && cp->mixed == mixed && cp->want_j == o->want_j && cp->want_k == o->want_k &&
-            cp->gen == h->list_gen && cp->tgen == tgen) {
+            cp->sym == o->symmetric_hint && cp->gen == h->list_gen && cp->tgen == tgen) {
             *out = cp;
             return JK_OK;
         }
@@ -1208,6 +1259,7 @@ int get_plan(jk_basis_s* h, int nd, const jk_build_opts* o, CachedPlan** out) {
     cp->mixed = mixed;
     cp->want_j = o->want_j;
     cp->want_k = o->want_k;
+    cp->sym = o->symmetric_hint;
     cp->gen = h->list_gen;
     cp->tgen = tgen;
     int rc = plan_work({MolRun{h, nd}}, o, kTileCapElems, cp->wp);
@@ -1235,7 +1287,7 @@ CachedPlan* find_plan(jk_basis_s* h, int nd, const jk_build_opts* o) {
     std::lock_guard<std::mutex> g(h->mu);
     for (CachedPlan* cp : h->plans)
         if (cp->nd == nd && cp->mixed == mixed && cp->want_j == o->want_j && cp->want_k == o->want_k &&
-            cp->gen == h->list_gen && cp->tgen == tgen)
+            cp->sym == o->symmetric_hint && cp->gen == h->list_gen && cp->tgen == tgen)
             return cp;
     return nullptr;
 }
@@ -1264,11 +1316,16 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     const int ndp = dens_stride(nd);
     const long long mat = static_cast<long long>(h->nc) * h->nc * ndp;
     double* DS = o->want_j ? reinterpret_cast<double*>(base + ms.off_DS) : nullptr;
+    const bool mixed = o->precision == JK_MIXED;
+    float* Df = mixed && o->want_k ? reinterpret_cast<float*>(base + ms.off_Df) : nullptr;
+    float* DSf = mixed && o->want_j ? reinterpret_cast<float*>(base + ms.off_DSf) : nullptr;
     hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, ndp, Dc, s);
     if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
     if (e == hipSuccess && DS)
         e = launch_pair_ds(Dc, h->nc, ndp, nd, h->d_pairs, static_cast<int>(h->pairs.size()), h->d_shell_nf,
                            h->d_ds_off, h->ns, DS, s);
+    if (e == hipSuccess && Df) e = launch_to_f32(Dc, Df, mat, s);
+    if (e == hipSuccess && DSf) e = launch_to_f32(DS, DSf, static_cast<long long>(h->ds_units) * ndp, s);
     if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
     if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
     if (e == hipSuccess && KTc) e = launch_zero(KTc, mat, s);
@@ -1282,6 +1339,8 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     md.KT = KTc;
     md.DS = DS;
     md.ds_off = h->d_ds_off;
+    md.Df = Df;
+    md.DSf = DSf;
     md.ns = h->ns;
     md.nc = h->nc;
     md.nd = nd;
@@ -1291,9 +1350,10 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
 
 // Outputs the build does not produce are never touched: their pointers are
 // dropped here (the caller may pass any value for them).
-hipError_t mol_post(const jk_basis_s* h, int nd, const MolDesc& md, double* J, double* K, hipStream_t s) {
-    return launch_cart2sph(md.J, md.K, md.KT, nd, h->nf, h->d_umap, h->nc, md.ndp, md.J ? J : nullptr,
-                           md.K ? K : nullptr, s);
+hipError_t mol_post(const jk_basis_s* h, int nd, const MolDesc& md, double* J, double* K, bool skip_t,
+                    hipStream_t s) {
+    return launch_cart2sph(md.J, md.K, skip_t ? md.K : md.KT, nd, h->nf, h->d_umap, h->nc, md.ndp,
+                           md.J ? J : nullptr, md.K ? K : nullptr, s);
 }
 
 int check_opts(const char* who, const jk_build_opts* o) {
@@ -1337,7 +1397,7 @@ size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o) {
     if (ensure_lists(h, o->schwarz_tol, o->precision == JK_MIXED ? o->fp32_bound : -1.0)) return 0;
     CachedPlan* cp = nullptr;
     if (get_plan(h, nd, o, &cp)) return 0;
-    return mol_space(h, nd, o).bytes + 2 * tile_bytes_of(cp->wp);
+    return mol_space(h, nd, o).bytes + 2 * kLanes * tile_bytes_of(cp->wp);
 }
 
 int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, const jk_build_opts* o) {
@@ -1362,7 +1422,7 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     hipStream_t s = static_cast<hipStream_t>(o->stream);
     const MolSpace ms = mol_space(h, nd, o);
     const size_t tb = tile_bytes_of(cp->wp);
-    const size_t total = ms.bytes + 2 * tb;
+    const size_t total = ms.bytes + 2 * kLanes * tb;
     char* ws = static_cast<char*>(o->workspace);
     bool own = false;
     if (ws) {
@@ -1381,9 +1441,9 @@ int jk_build(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, co
     MolDesc md{};
     hipError_t e = mol_pre(h, nd, D, o, ws, ms, md, s);
     if (e == hipSuccess)
-        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, ws + ms.bytes + tb, o, h->d_boys,
-                     h->d_boys32, s, h);
-    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, s);
+        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, tb, o, h->d_boys, h->d_boys32, s,
+                     h->aux, h);
+    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, cp->wp.skip_t, s);
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (e == hipSuccess) e = e2;
@@ -1420,7 +1480,7 @@ int jk_build_noalloc(jk_basis_t h, int32_t nd, const double* D, double* J, doubl
                     nd);
     const MolSpace ms = mol_space(h, nd, o);
     const size_t tb = tile_bytes_of(cp->wp);
-    const size_t total = ms.bytes + 2 * tb;
+    const size_t total = ms.bytes + 2 * kLanes * tb;
     if (total > kNoAllocScratchBytes)
         return fail(JK_ENOMEM,
                     "jk_build_noalloc: the build needs %zu bytes of workspace, above the %zu of the static buffer",
@@ -1431,9 +1491,9 @@ int jk_build_noalloc(jk_basis_t h, int32_t nd, const double* D, double* J, doubl
     MolDesc md{};
     hipError_t e = mol_pre(h, nd, D, o, ws, ms, md, s);
     if (e == hipSuccess)
-        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, ws + ms.bytes + tb, o, h->d_boys,
-                     h->d_boys32, s, nullptr);
-    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, s);
+        e = run_plan(cp->wp, cp->d_eri, cp->d_dig, md, nullptr, ws + ms.bytes, tb, o, h->d_boys, h->d_boys32, s,
+                     nullptr, nullptr);   // one launch lane: no events or helper-stream work
+    if (e == hipSuccess) e = mol_post(h, nd, md, J, K, cp->wp.skip_t, s);
     if (e != hipSuccess) return fail(JK_EDEVICE, "jk_build_noalloc: %s", hipGetErrorString(e));
     {
         std::lock_guard<std::mutex> g(h->mu);
@@ -1454,7 +1514,7 @@ struct BatchSetup {
     WorkPlan wp;
     std::vector<MolSpace> ms;
     std::vector<size_t> mol_off;
-    size_t off_tiles = 0, off_scr = 0, off_items = 0, total = 0;
+    size_t off_tiles = 0, tb = 0, off_items = 0, total = 0;
     size_t eri_bytes = 0, dig_bytes[2] = {0, 0}, mol_bytes = 0;
 };
 
@@ -1478,10 +1538,9 @@ int batch_setup(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const jk_
         off += b.ms.back().bytes;
     }
     const size_t tb = tile_bytes_of(b.wp);
-    b.off_tiles = off;
-    off += tb;
-    b.off_scr = off;
-    off += tb;
+    b.tb = tb;
+    b.off_tiles = off;             // kLanes pairs of (integral work buffer, scratch)
+    off += 2 * kLanes * tb;
     b.off_items = off;
     b.eri_bytes = al256(std::max<size_t>(1, b.wp.eri.size()) * sizeof(EriItem));
     b.dig_bytes[0] = al256(std::max<size_t>(1, b.wp.dig[0].size()) * sizeof(DigItem));
@@ -1568,10 +1627,10 @@ int jk_build_batch(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const 
         else std::free(stage);
     }
     if (e == hipSuccess)
-        e = run_plan(b.wp, d_eri, d_dig, mds[0], d_mols, ws + b.off_tiles, ws + b.off_scr, o, hs[0]->d_boys,
-                     hs[0]->d_boys32, s, nullptr);
+        e = run_plan(b.wp, d_eri, d_dig, mds[0], d_mols, ws + b.off_tiles, b.tb, o, hs[0]->d_boys,
+                     hs[0]->d_boys32, s, hs[0]->aux, nullptr);
     for (int i = 0; i < nmol && e == hipSuccess; ++i)
-        e = mol_post(hs[i], nd[i], mds[i], o->want_j ? J[i] : nullptr, o->want_k ? K[i] : nullptr, s);
+        e = mol_post(hs[i], nd[i], mds[i], o->want_j ? J[i] : nullptr, o->want_k ? K[i] : nullptr, b.wp.skip_t, s);
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (e == hipSuccess) e = e2;

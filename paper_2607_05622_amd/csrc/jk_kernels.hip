@@ -105,6 +105,12 @@ __global__ void k_pair_dmax(const double* __restrict__ Dc, int nc, int ndp, int 
     dmax[t] = m;
 }
 
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * blockDim.x)
+        dst[i] = static_cast<float>(src[i]);
+}
+
 __global__ void k_zero(double* __restrict__ p, long long n) {
     for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -200,6 +206,14 @@ void* static_scratch(int dev) {
     if (dev < 0 || dev >= kMaxDevices) return nullptr;
     std::lock_guard<std::mutex> g(g_scratch_mu);
     return g_scratch_addr[dev];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_to_f32, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(double* p, long long n, hipStream_t s) {

@@ -37,13 +37,15 @@ struct MolDesc {
     double* KT;             // exchange, transposed contributions (K += KT^T at the end)
     const double* DS;       // D + D^T per shell pair (c >= d): [unit][ndp], unit = ds_off[c][d] + k ND + l
     const int* ds_off;      // [ns][ns]: first unit of shell pair (c, d), c >= d in internal order
+    const float* Df;        // FP32 copies of D and DS (mixed builds; FP32-tier digestion)
+    const float* DSf;
     int ns, nc, nd, ndp;
     int pslots, pad;        // entries per primitive-pair plane
 };
 // load_mol reads the fields at these offsets
 static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ds_off) == 64 &&
-                  __builtin_offsetof(MolDesc, ns) == 72 && __builtin_offsetof(MolDesc, pslots) == 88 &&
-                  sizeof(MolDesc) == 96,
+                  __builtin_offsetof(MolDesc, DSf) == 80 && __builtin_offsetof(MolDesc, ns) == 88 &&
+                  __builtin_offsetof(MolDesc, pslots) == 104 && sizeof(MolDesc) == 112,
               "MolDesc layout");
 
 // A contiguous run of one molecule's class list whose tiles occupy
@@ -103,6 +105,7 @@ struct DigestArgs {
     const void* tiles;      // [NF][n] per tile item, double or float
     void* dcopy;            // D-order copy [n][NF] per tile item, written by pass C
     int want_j, want_k;
+    int skip_t;             // D == D^T promised: the D^T contractions (KT) are not digested
     unsigned nblocks;       // 8 x the largest per-XCD task count
 };
 
@@ -133,6 +136,8 @@ hipError_t launch_pair_ds(const double* Dc, int nc, int ndp, int nd, const PairI
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,
                             int ns, double* dmax, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
+// dst[i] = (float) src[i], i < n
+hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
 
 // Static workspace of jk_build_noalloc (bytes per device).
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;

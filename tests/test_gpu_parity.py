@@ -162,6 +162,21 @@ def test_structure_of_gpu_results(dev):
     assert maxabs(K[2], K[0].T) <= 1e-12 * sc          # K(D^T) = K(D)^T
 
 
+def test_symmetric_hint_skips_transposed_exchange(dev):
+    """Symmetric densities with symmetric_hint = 1 (the D^T exchange
+    contractions skipped, K = Kc + Kc^T): the same J and K as without the
+    hint, and the oracle's, for more than 8 densities (where it applies) and
+    for fewer (where it is ignored)."""
+    b = synth.random_basis(410, 4, 3)
+    for nd in (12, 5):
+        D = synth.random_densities(411 + nd, nd, b.nbf(), symmetric=True)
+        Jr, Kr = oracle.jk(b, D, 1e-12)
+        J0, K0 = gpu_jk(b, D, dev)
+        J1, K1 = gpu_jk(b, D, dev, symmetric_hint=1)
+        assert maxabs(J1, J0) <= 1e-12 and maxabs(K1, K0) <= 1e-12, nd
+        assert maxabs(J1, Jr) <= TOL and maxabs(K1, Kr) <= TOL, nd
+
+
 def test_repeat_determinism(dev):
     b = synth.random_basis(505, 5, 3)
     D = synth.random_densities(5, 8, b.nbf())
