@@ -33,7 +33,7 @@ __device__ __forceinline__ gptr<T> glob(T* p) {
 __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& mol0, int i) {
     if (!mols) return mol0;
     const gptr<const unsigned long long> w = (gptr<const unsigned long long>)(mols + i);
-    const gptr<const int> n = (gptr<const int>)(w + 11);
+    const gptr<const int> n = (gptr<const int>)(w + 13);
     MolDesc m;
     m.pairs = reinterpret_cast<const PairInfo*>(w[0]);
     m.prims = reinterpret_cast<const double*>(w[1]);
@@ -46,6 +46,8 @@ __device__ __forceinline__ MolDesc load_mol(const MolDesc* mols, const MolDesc& 
     m.ds_off = reinterpret_cast<const int*>(w[8]);
     m.Df = reinterpret_cast<const float*>(w[9]);
     m.DSf = reinterpret_cast<const float*>(w[10]);
+    m.DT = reinterpret_cast<const double*>(w[11]);
+    m.DTf = reinterpret_cast<const float*>(w[12]);
     m.ns = n[0];
     m.nc = n[1];
     m.nd = n[2];

@@ -61,6 +61,7 @@ struct DigMma<double> {
     static __device__ __forceinline__ V step(double a, double b, V c) { return mfma_f64(a, b, c); }
     static __device__ __forceinline__ int row(int e, int r4) { return 4 * e + r4; }
     static __device__ __forceinline__ const double* dens(const MolDesc& m) { return m.D; }
+    static __device__ __forceinline__ const double* dtrans(const MolDesc& m) { return m.DT; }
     static __device__ __forceinline__ const double* dsym(const MolDesc& m) { return m.DS; }
 };
 template <>
@@ -71,6 +72,7 @@ struct DigMma<float> {
     }
     static __device__ __forceinline__ int row(int e, int r4) { return 4 * r4 + e; }
     static __device__ __forceinline__ const float* dens(const MolDesc& m) { return m.Df; }
+    static __device__ __forceinline__ const float* dtrans(const MolDesc& m) { return m.DTf; }
     static __device__ __forceinline__ const float* dsym(const MolDesc& m) { return m.DSf; }
 };
 
@@ -152,22 +154,24 @@ struct DigShape {
 
 // Density access of one lane.  The lane's MFMA column is density x; its K
 // contractions read D[F][V] (tr = false) or D[V][F] (tr = true) for a fixed
-// bra-side function F and a ket-side function V.
+// bra-side function F and a ket-side function V.  D[V][F] is read as
+// DT[F][V] from the transposed copy, so both forms walk the bra rows F.
 template <typename R = double>
 struct DigLane {
     int x;
     bool tr;
-    long long sRow, ndp, sF, sV;
-    gptr<const R> Dx;
+    long long sRow, ndp;
+    gptr<const R> Dx, DTx, Kx;
     __device__ DigLane(const MolDesc& m, int x_, bool tr_) : x(x_), tr(tr_) {
         ndp = m.ndp;
         sRow = static_cast<long long>(m.nc) * ndp;
-        sF = tr ? ndp : sRow;
-        sV = tr ? sRow : ndp;
         Dx = glob(DigMma<R>::dens(m)) + x;
+        DTx = glob(DigMma<R>::dtrans(m)) + x;
+        Kx = tr ? DTx : Dx;
     }
     __device__ __forceinline__ R d(long long r, long long c) const { return Dx[r * sRow + c * ndp]; }
-    __device__ __forceinline__ R dk(long long F, long long V) const { return Dx[F * sF + V * sV]; }
+    __device__ __forceinline__ R dt(long long r, long long c) const { return DTx[r * sRow + c * ndp]; }
+    __device__ __forceinline__ R dk(long long F, long long V) const { return Kx[F * sRow + V * ndp]; }
 };
 
 // Fold weight of a canonical quartet from its shells: 1/2 for a = b, for

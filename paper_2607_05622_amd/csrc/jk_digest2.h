@@ -242,12 +242,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
                         b3[j] = L.dk(fb + j, V0 + l);
-                        if constexpr (G16) t3[j] = L.d(V0 + l, fb + j);
+                        if constexpr (G16) t3[j] = L.dt(fb + j, V0 + l);
                     }
 #pragma unroll
                     for (int i = 0; i < NA; ++i) {
                         b4[i] = L.dk(fa + i, V0 + l);
-                        if constexpr (G16) t4[i] = L.d(V0 + l, fa + i);
+                        if constexpr (G16) t4[i] = L.dt(fa + i, V0 + l);
                     }
 #pragma unroll
                     for (int j = 0; j < NB; ++j)
@@ -388,12 +388,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
                     b5[j] = L.dk(fb + j, V0 + k);
-                    if constexpr (G16) t5[j] = L.d(V0 + k, fb + j);
+                    if constexpr (G16) t5[j] = L.dt(fb + j, V0 + k);
                 }
 #pragma unroll
                 for (int i = 0; i < NA; ++i) {
                     b6[i] = L.dk(fa + i, V0 + k);
-                    if constexpr (G16) t6[i] = L.d(V0 + k, fa + i);
+                    if constexpr (G16) t6[i] = L.dt(fa + i, V0 + k);
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j)

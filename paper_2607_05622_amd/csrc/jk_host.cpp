@@ -795,7 +795,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
 
 // Per-molecule workspace: densities and accumulators.
 struct MolSpace {
-    size_t off_D, off_J, off_K, off_KT, off_dmax, off_DS, off_Df, off_DSf, bytes;
+    size_t off_D, off_J, off_K, off_KT, off_dmax, off_DS, off_Df, off_DSf, off_DT, off_DTf, bytes;
 };
 
 inline size_t al256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -823,6 +823,13 @@ MolSpace mol_space(const jk_basis_s* h, int nd, const jk_build_opts* o) {
     if (mixed && o->want_k) off += al256(mat / 2);
     m.off_DSf = off;
     if (mixed && o->want_j) off += al256(ds * sizeof(float));
+    // transposed densities for the D^T exchange contractions (D itself when
+    // the caller promises symmetric densities)
+    const bool dt = o->want_k && !o->symmetric_hint;
+    m.off_DT = off;
+    if (dt) off += al256(mat);
+    m.off_DTf = off;
+    if (dt && mixed) off += al256(mat / 2);
     m.bytes = off;
     return m;
 }
@@ -1319,12 +1326,17 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     const bool mixed = o->precision == JK_MIXED;
     float* Df = mixed && o->want_k ? reinterpret_cast<float*>(base + ms.off_Df) : nullptr;
     float* DSf = mixed && o->want_j ? reinterpret_cast<float*>(base + ms.off_DSf) : nullptr;
+    const bool dt = o->want_k && !o->symmetric_hint;
+    double* DT = dt ? reinterpret_cast<double*>(base + ms.off_DT) : nullptr;
+    float* DTf = dt && mixed ? reinterpret_cast<float*>(base + ms.off_DTf) : nullptr;
     hipError_t e = launch_sph2cart(D, nd, h->nf, h->d_cmap, h->nc, ndp, Dc, s);
     if (e == hipSuccess) e = launch_pair_dmax(Dc, h->nc, ndp, nd, h->d_shell_f0, h->d_shell_nf, h->ns, dmax, s);
     if (e == hipSuccess && DS)
         e = launch_pair_ds(Dc, h->nc, ndp, nd, h->d_pairs, static_cast<int>(h->pairs.size()), h->d_shell_nf,
                            h->d_ds_off, h->ns, DS, s);
     if (e == hipSuccess && Df) e = launch_to_f32(Dc, Df, mat, s);
+    if (e == hipSuccess && DT) e = launch_transpose(Dc, h->nc, ndp, DT, s);
+    if (e == hipSuccess && DTf) e = launch_to_f32(DT, DTf, mat, s);
     if (e == hipSuccess && DSf) e = launch_to_f32(DS, DSf, static_cast<long long>(h->ds_units) * ndp, s);
     if (e == hipSuccess && Jc) e = launch_zero(Jc, mat, s);
     if (e == hipSuccess && Kc) e = launch_zero(Kc, mat, s);
@@ -1341,6 +1353,8 @@ hipError_t mol_pre(const jk_basis_s* h, int nd, const double* D, const jk_build_
     md.ds_off = h->d_ds_off;
     md.Df = Df;
     md.DSf = DSf;
+    md.DT = DT ? DT : Dc;      // symmetric_hint: D^T = D
+    md.DTf = DTf ? DTf : Df;
     md.ns = h->ns;
     md.nc = h->nc;
     md.nd = nd;

@@ -105,6 +105,17 @@ __global__ void k_pair_dmax(const double* __restrict__ Dc, int nc, int ndp, int 
     dmax[t] = m;
 }
 
+__global__ void k_transpose(const double* __restrict__ D, int nc, int ndp, double* __restrict__ DT) {
+    const long long n = static_cast<long long>(nc) * nc * ndp;
+    for (long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const long long ij = e / ndp;
+        const int x = static_cast<int>(e - ij * ndp);
+        const int i = static_cast<int>(ij / nc), j = static_cast<int>(ij - static_cast<long long>(i) * nc);
+        DT[e] = D[(static_cast<long long>(j) * nc + i) * ndp + x];
+    }
+}
+
 __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
     for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -206,6 +217,14 @@ void* static_scratch(int dev) {
     if (dev < 0 || dev >= kMaxDevices) return nullptr;
     std::lock_guard<std::mutex> g(g_scratch_mu);
     return g_scratch_addr[dev];
+}
+
+hipError_t launch_transpose(const double* D, int nc, int ndp, double* DT, hipStream_t s) {
+    const long long n = static_cast<long long>(nc) * nc * ndp;
+    long long g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_transpose, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, D, nc, ndp, DT);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t s) {

@@ -39,13 +39,16 @@ struct MolDesc {
     const int* ds_off;      // [ns][ns]: first unit of shell pair (c, d), c >= d in internal order
     const float* Df;        // FP32 copies of D and DS (mixed builds; FP32-tier digestion)
     const float* DSf;
+    const double* DT;       // transposed densities DT[i][j][x] = D[j][i][x] (the D^T exchange contractions)
+    const float* DTf;       // its FP32 copy (mixed builds)
     int ns, nc, nd, ndp;
     int pslots, pad;        // entries per primitive-pair plane
 };
 // load_mol reads the fields at these offsets
 static_assert(__builtin_offsetof(MolDesc, KT) == 48 && __builtin_offsetof(MolDesc, ds_off) == 64 &&
-                  __builtin_offsetof(MolDesc, DSf) == 80 && __builtin_offsetof(MolDesc, ns) == 88 &&
-                  __builtin_offsetof(MolDesc, pslots) == 104 && sizeof(MolDesc) == 112,
+                  __builtin_offsetof(MolDesc, DSf) == 80 && __builtin_offsetof(MolDesc, DTf) == 96 &&
+                  __builtin_offsetof(MolDesc, ns) == 104 && __builtin_offsetof(MolDesc, pslots) == 120 &&
+                  sizeof(MolDesc) == 128,
               "MolDesc layout");
 
 // A contiguous run of one molecule's class list whose tiles occupy
@@ -136,6 +139,8 @@ hipError_t launch_pair_ds(const double* Dc, int nc, int ndp, int nd, const PairI
 hipError_t launch_pair_dmax(const double* Dc, int nc, int ndp, int nd, const int* shell_f0, const int* shell_nf,
                             int ns, double* dmax, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
+// DT[i][j][x] = D[j][i][x] for an nc x nc matrix of ndp-vectors
+hipError_t launch_transpose(const double* D, int nc, int ndp, double* DT, hipStream_t s);
 // dst[i] = (float) src[i], i < n
 hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
 

@@ -441,11 +441,12 @@ def test_batch_mixed_precision(dev):
         assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8)
 
 
-def test_batch_workload_64_molecules(dev, capsys):
-    """The 64-molecule uneven workload in one batched build: every molecule
-    equals its own build; the eight smallest against the whole oracle build,
-    the four largest on sampled shell-pair blocks.  Reports progress on the
-    terminal even when output is captured."""
+def test_batch_workload_64_molecules(dev, capsys, tmp_path):
+    """The 64-molecule uneven workload in one batched build, with schedules
+    from the autotuner (run on the batch's largest molecule, cached as JSON
+    and loaded): every molecule equals its own build; the eight smallest
+    against the whole oracle build, the four largest on sampled shell-pair
+    blocks.  Reports progress on the terminal even when output is captured."""
     import torch
 
     def note(msg):
@@ -461,8 +462,16 @@ def test_batch_workload_64_molecules(dev, capsys):
         hs.append(jk.JKBasis(b))
         if i % 8 == 7:
             note(f"{i + 1} handles created")
+    old_tune = [jk.jk_tune_get(c) for c in range(21)]
     try:
         Dt = [torch.tensor(D, device=dev) for D in Ds]
+        big = int(np.argmax([b.nbf() for b in bases]))
+        cache = str(tmp_path / "tune_batch.json")
+        jk.jk_autotune(hs[big].h, Dt[big], torch.empty_like(Dt[big]), torch.empty_like(Dt[big]), cache_path=cache)
+        for c in range(21):
+            jk.jk_tune_set(c)
+        jk.jk_tune_load(cache)
+        note(f"schedules tuned on molecule {big} ({bases[big].nbf()} AO) and loaded from {cache}")
         Jt, Kt = jk.jk_build_batch([h.h for h in hs], Dt)
         torch.cuda.synchronize()
         Jb = [J.cpu().numpy() for J in Jt]
@@ -475,6 +484,8 @@ def test_batch_workload_64_molecules(dev, capsys):
     finally:
         for h in hs:
             h.close()
+        for c, t in enumerate(old_tune):
+            jk.jk_tune_set(c, **t)
     note("each molecule equals its own build")
     order = np.argsort([b.nbf() for b in bases])
     for i in order[:8]:
