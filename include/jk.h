@@ -222,7 +222,10 @@ int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
 
 /* Kernel timing for measurement.  jk_profile_enable(h, 1) makes every later
  * jk_build on h record a HIP event pair around each integral and digestion
- * launch, on the build's stream; jk_profile_read synchronizes those events
+ * launch, on the build's stream, and run the build's launches one after
+ * another on that stream (unprofiled builds alternate them between the
+ * caller's stream and a helper stream), so each kernel's time is its own;
+ * jk_profile_read synchronizes those events
  * and returns, per kernel, totals since the last read, then clears them.
  * kind 0 = integral (ERI tile) kernel, 1 = digestion pass C (J, and K
  * over runs of equal ket shell c), 4 = digestion pass D (K over runs of

@@ -1156,7 +1156,8 @@ hipError_t run_plan(const WorkPlan& wp, const EriItem* d_eri, DigItem* const d_d
                     const MolDesc* d_mols, char* work, size_t tb, const jk_build_opts* o, const double* boys,
                     const float* boys32, hipStream_t s, hipStream_t aux, jk_basis_s* prof) {
     hipError_t e = hipSuccess;
-    const int lanes = (aux && wp.launches.size() > 1) ? kLanes : 1;
+    // while profiling, one lane: every kernel's event time is then its own
+    const int lanes = (aux && wp.launches.size() > 1 && !(prof && prof->profiling)) ? kLanes : 1;
     hipEvent_t fork = nullptr, join = nullptr;
     if (lanes > 1) {
         e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
