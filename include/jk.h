@@ -157,7 +157,8 @@ size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t
  *   dig_kernel 1 (default): a workgroup stages each chunk of tiles once for
  *              waves of different roles; 2: every wave owns a task and all
  *              its roles (classes of at most 408 functions per quartet;
- *              others use 1);
+ *              others use 1); 3: as 1 in one pass over runs of equal ket
+ *              shell c, the two K blocks indexed by d added per quartet;
  *   eri_block  quartets (threads) per integral workgroup: 64, 128 or 256
  *              (default).
  * The paper launches integral work per realized bucket and notes that the

@@ -29,7 +29,8 @@ hipError_t launch_eri_tpl(const EriTileArgs& a, hipStream_t s) {
 // Digestion.  kernel 2: wave-private tasks (jk_digest2.h), four per
 // workgroup, for classes of at most 408 functions per quartet.  Otherwise
 // one workgroup per task; pass C has a J wave and one K wave per density
-// form, pass D one K wave per density form.
+// form, pass D one K wave per density form; kernel 3 is pass C in its
+// one-pass form.
 template <int la, int lb, int lc, int ld, typename TT>
 hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g16, int kernel) {
     constexpr int nf = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
@@ -47,7 +48,14 @@ hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g
     }
     const dim3 grid(a.nblocks);
     // 16-density groups: the last wave takes the D^T contractions, left out
-    // when the densities are symmetric
+    // when the densities are symmetric.  kernel 3: pass C alone takes all
+    // four K blocks (its plans have no pass D items).
+    if (kernel == 3) {
+        if (pass != 0) return hipSuccess;
+        if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true, true>), grid, dim3(a.skip_t ? 128 : 192), 0, s, a);
+        else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false, true>), grid, dim3(128), 0, s, a);
+        return hipGetLastError();
+    }
     if (pass == 0) {
         if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(a.skip_t ? 128 : 192), 0, s, a);
         else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, dim3(128), 0, s, a);

@@ -219,9 +219,94 @@ __device__ __forceinline__ int dig_chunk(gptr<const long long> kin, int p, int p
     return more ? QB : n;
 }
 
+// K_ad += I D_bc and K_bd += I D_ac for the n quartets of a staged chunk
+// whose ket shell c (first function fc) is shared and whose d functions
+// start at sV[q]: output rows (q, i, l) and (q, j, l), contraction over
+// (j, k) and (i, k) against density operands fixed for the chunk.  Adds
+// each finished row into K (or KT for the D^T contraction).
+template <int LA, int LB, int LC, int LD, int QB, typename R>
+__device__ __forceinline__ void dig_kd_rows(const MolDesc& m, const DigLane<R>& L, int r4, int c16, const R* sT,
+                                            const int* sV, int n, int fa, int fb, int fc) {
+    using MM = DigMma<R>;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NCD = NC * ND, QBP = QB + 1;
+    constexpr int RAD = NA * ND, RBD = NB * ND;                 // output rows per quartet
+    constexpr int KAD = (NB * NC + 3) / 4, KBD = (NA * NC + 3) / 4;   // k-steps
+    constexpr int MAD = (QB * RAD + 15) / 16, MBD = (QB * RBD + 15) / 16;
+    const long long nc = m.nc;
+    double* const out = L.tr ? m.KT : m.K;
+    // the density operands of the chunk: D_bc at k-row (j, k), D_ac at (i, k)
+    R bad[KAD], bbd[KBD];
+#pragma unroll
+    for (int t = 0; t < KAD; ++t) {
+        const int kk = 4 * t + r4;
+        bad[t] = kk < NB * NC ? L.dk(fb + kk / NC, fc + kk % NC) : R(0);
+    }
+#pragma unroll
+    for (int t = 0; t < KBD; ++t) {
+        const int kk = 4 * t + r4;
+        bbd[t] = kk < NA * NC ? L.dk(fa + kk / NC, fc + kk % NC) : R(0);
+    }
+    // K_ad: row (q, i, l), k-row (j, k) of tile function ((i NB + j) NC + k) ND + l
+#pragma unroll 1
+    for (int mt = 0; mt < MAD; ++mt) {
+        if (mt * 16 >= n * RAD) break;
+        const int r = mt * 16 + c16;
+        const int q = r < n * RAD ? r / RAD : 0, u = r < n * RAD ? r - (r / RAD) * RAD : 0;
+        const int i = u / ND, l = u - (u / ND) * ND;
+        typename MM::V v = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KAD; ++t) {
+            const int kk = 4 * t + r4 < NB * NC ? 4 * t + r4 : NB * NC - 1;
+            const int j = kk / NC, k = kk - (kk / NC) * NC;
+            v = MM::step(sT[(((i * NB + j) * NC + k) * ND + l) * QBP + q], bad[t], v);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int mo = mt * 16 + MM::row(e, r4);
+            const int qo = mo / RAD, uo = mo - (mo / RAD) * RAD;
+            if (qo < n && L.x < m.nd) {
+                const int io = uo / ND, lo = uo - (uo / ND) * ND;
+                gadd(out + ((fa + io) * nc + sV[qo] + lo) * L.ndp + L.x, static_cast<double>(v[e]));
+            }
+        }
+    }
+    // K_bd: row (q, j, l), k-row (i, k)
+#pragma unroll 1
+    for (int mt = 0; mt < MBD; ++mt) {
+        if (mt * 16 >= n * RBD) break;
+        const int r = mt * 16 + c16;
+        const int q = r < n * RBD ? r / RBD : 0, u = r < n * RBD ? r - (r / RBD) * RBD : 0;
+        const int j = u / ND, l = u - (u / ND) * ND;
+        typename MM::V v = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KBD; ++t) {
+            const int kk = 4 * t + r4 < NA * NC ? 4 * t + r4 : NA * NC - 1;
+            const int i = kk / NC, k = kk - (kk / NC) * NC;
+            v = MM::step(sT[(((i * NB + j) * NC + k) * ND + l) * QBP + q], bbd[t], v);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int mo = mt * 16 + MM::row(e, r4);
+            const int qo = mo / RBD, uo = mo - (mo / RBD) * RBD;
+            if (qo < n && L.x < m.nd) {
+                const int jo = uo / ND, lo = uo - (uo / ND) * ND;
+                gadd(out + ((fb + jo) * nc + sV[qo] + lo) * L.ndp + L.x, static_cast<double>(v[e]));
+            }
+        }
+    }
+}
+
 // Pass C: J_ab, J_cd (wave 0), K_ac, K_bc (the other waves) over runs of
 // equal ket shell c, and the D-order copy of the tiles for pass D.
-template <int LA, int LB, int LC, int LD, typename TT, bool G16>
+//
+// One-pass form (OP): the K waves also take K_ad and K_bd, so there is no
+// pass D and no copy.  Over a run of equal c their density operands D_bc
+// and D_ac are fixed (loaded once per chunk) while the output block moves
+// with d; so, like J_cd, they are contracted with one output row per
+// (quartet, bra function, d function), which fills the matrix-core rows,
+// and each row is added to K as it is finished.
+template <int LA, int LB, int LC, int LD, typename TT, bool G16, bool OP = false>
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(DigShape<LA, LB, LC, LD>::WAVES_C)))
 void k_digest_c(DigestArgs a) {
     using S = DigShape<LA, LB, LC, LD>;
@@ -309,7 +394,7 @@ void k_digest_c(DigestArgs a) {
             if (idx < NF * QB) sT[f * QBP + qb] = w * t;
         }
         lds_barrier();
-        if (a.want_k && grp == 0) {
+        if (!OP && a.want_k && grp == 0) {
             const gptr<TT> cp = glob(static_cast<TT*>(a.dcopy)) + it.tile_off;
             for (int idx = static_cast<int>(threadIdx.x); idx < n * NF; idx += static_cast<int>(blockDim.x)) {
                 const int qb = idx / NF, f = idx - (idx / NF) * NF;
@@ -393,6 +478,7 @@ void k_digest_c(DigestArgs a) {
             }
 #pragma unroll
             for (int t = 0; t < M3 + M4; ++t) acc[t].fold();
+            if constexpr (OP) dig_kd_rows<LA, LB, LC, LD, QB, R>(m, L, r4, c16, sT, sV, n, fa, fb, fc);
             if (!more) {
 #pragma unroll
                 for (int t = 0; t < M3; ++t)

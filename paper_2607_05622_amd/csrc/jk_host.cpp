@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -668,9 +669,23 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
             // through its L2; blocks go to the XCD with the least work so far.
             std::vector<DigItem> xq[2][8];
             int xtasks[2][8] = {};
-            double xwork[8] = {};
+            // the launch's blocks in list order: their items per pass, and work
+            std::vector<std::array<DigItem, 2>> pend;
+            std::vector<double> pwork;
+            int npass = 1;
             auto flush = [&]() {
                 if (L.neri > 0) {
+                    double xwork[8] = {};
+                    for (size_t k = 0; k < pend.size(); ++k) {
+                        const int x = static_cast<int>(std::min_element(xwork, xwork + 8) - xwork);
+                        xwork[x] += pwork[k];
+                        for (int ps = 0; ps < npass; ++ps) {
+                            DigItem d = pend[k][ps];
+                            d.kstart = xtasks[ps][x];
+                            xtasks[ps][x] += d.nparts * d.ngroups;
+                            xq[ps][x].push_back(d);
+                        }
+                    }
                     for (int ps = 0; ps < 2; ++ps) {
                         size_t kmax = 0;
                         int tmax = 0;
@@ -692,7 +707,8 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     for (auto& w : v) w.clear();
                 for (auto& v : xtasks)
                     for (int& t : v) t = 0;
-                for (double& w : xwork) w = 0.0;
+                pend.clear();
+                pwork.clear();
                 LaunchRec fresh;
                 fresh.cls = c;
                 fresh.fp32 = fp32;
@@ -741,11 +757,14 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     wp.eri.push_back(e);
                     L.neri++;
                     L.eri_blocks += (n + tn.eri_block - 1) / tn.eri_block;
+                    // one-pass digestion (kernel 3) has no pass D
+                    npass = o->want_k && tn.dig_kernel != 3 ? 2 : 1;
                     for (int k = b0; k < b1; ++k) {
-                        const int x = static_cast<int>(std::min_element(xwork, xwork + 8) - xwork);
-                        xwork[x] += static_cast<double>(CL.blocks[k].y) * ngroups;
-                        for (int ps = 0; ps < (o->want_k ? 2 : 1); ++ps) {
-                            DigItem d{};
+                        pend.emplace_back();
+                        pwork.push_back(static_cast<double>(CL.blocks[k].y) * ngroups);
+                        for (int ps = 0; ps < npass; ++ps) {
+                            DigItem& d = pend.back()[ps];
+                            d = DigItem{};
                             d.kin = ps ? CL.dev_kind : CL.dev_kin;
                             d.pos = CL.dev_pos;
                             d.bra = CL.block_bra[k];
@@ -757,10 +776,7 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                             d.parts = CL.dev_parts[ps] + CL.part_off[ps][k];
                             d.nparts = CL.part_off[ps][k + 1] - CL.part_off[ps][k];
                             d.ngroups = ngroups;
-                            d.kstart = xtasks[ps][x];
                             d.mol = static_cast<int>(mi);
-                            xtasks[ps][x] += d.nparts * ngroups;
-                            xq[ps][x].push_back(d);
                         }
                     }
                     const double ef = n * (prim_avg * (kClassCost[c].prim_flops + kClassCost[c].vrr_flops) +
@@ -768,8 +784,9 @@ int plan_work(const std::vector<MolRun>& mols, const jk_build_opts* o, long long
                     // pass C: J_ab and J_cd (2 FMA), K_ac and K_bc with D and D^T (4 FMA);
                     // pass D: K_ad and K_bd with D and D^T (4 FMA) per function quartet and density
                     const double fq = static_cast<double>(n) * NF * nd;
-                    const double dfc = fq * 2.0 * ((o->want_j ? 2 : 0) + (o->want_k ? 4 : 0));
-                    const double dfd = fq * 2.0 * (o->want_k ? 4 : 0);
+                    const bool one = tn.dig_kernel == 3;
+                    const double dfc = fq * 2.0 * ((o->want_j ? 2 : 0) + (o->want_k ? (one ? 8 : 4) : 0));
+                    const double dfd = one ? 0.0 : fq * 2.0 * (o->want_k ? 4 : 0);
                     const double df = dfc + dfd;
                     L.eri_flops += ef;
                     L.dig_flops[0] += dfc;
@@ -1661,7 +1678,7 @@ int jk_build_batch(int32_t nmol, const jk_basis_t* hs, const int32_t* nd, const 
 int jk_tune_set(int32_t cls, const jk_tune_t* t) {
     if (cls < 0 || cls >= kNumClass || !t || t->seg_max < 4 || t->seg_max > (1 << 20) ||
         !(t->g_max == 1 || t->g_max == 2 || t->g_max == 4 || t->g_max == 8 || t->g_max == 16) ||
-        !(t->dig_kernel == 1 || t->dig_kernel == 2) ||
+        !(t->dig_kernel >= 1 && t->dig_kernel <= 3) ||
         !(t->eri_block == 64 || t->eri_block == 128 || t->eri_block == 256))
         return fail(JK_EINVAL, "jk_tune_set: bad arguments");
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -1766,7 +1783,7 @@ int jk_autotune(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
     // coordinate search: digestion kernel x density group, then piece
     // length, then integral workgroup size, each around the best so far
     int rc;
-    for (int k : {1, 2})
+    for (int k : {1, 2, 3})
         for (int g : {16, 8})
             if ((rc = trial([&](int, jk_tune_t& t) { t.dig_kernel = k; t.g_max = g; }))) return rc;
     for (int seg : {32, 64, 128, 256})

@@ -106,7 +106,7 @@ def test_tune_table_and_cache(tmp_path, lib):
     try:
         jk.jk_tune_set(3, 512, 8, 2, 64)
         assert jk.jk_tune_get(3) == dict(seg_max=512, g_max=8, dig_kernel=2, eri_block=64)
-        for bad in [(-1, 256, 4), (21, 256, 4), (0, 0, 4), (0, 256, 3), (0, 256, 32), (0, 256, 16, 3),
+        for bad in [(-1, 256, 4), (21, 256, 4), (0, 0, 4), (0, 256, 3), (0, 256, 32), (0, 256, 16, 4),
                     (0, 256, 16, 1, 32), (0, 256, 16, 1, 512)]:
             with pytest.raises(jk.JKError):
                 jk.jk_tune_set(*bad)

@@ -92,6 +92,30 @@ def test_spd_molecule_ragged_nd(dev, nd):
     assert maxabs(J, Jr) <= TOL and maxabs(K, Kr) <= TOL
 
 
+@pytest.mark.parametrize("dig_kernel", [1, 2, 3])
+def test_every_digestion_kernel(dev, dig_kernel):
+    """Each digestion kernel the tunables select (1: one workgroup per
+    task; 2: wave-private tasks; 3: one pass, K_ad and K_bd per quartet),
+    with 16- and 8-density groups, FP64 and mixed, against the oracle on a
+    5-atom s/p/d molecule with 17 densities (a ragged last group), short
+    pieces so every bra pair spans several."""
+    b = synth.random_basis(731, 5, 3)
+    D = synth.random_densities(732, 17, b.nbf())
+    Jr, Kr = oracle.jk(b, D, 1e-12)
+    old = [jk.jk_tune_get(c) for c in range(21)]
+    try:
+        for g in (16, 8):
+            for c in range(21):
+                jk.jk_tune_set(c, seg_max=16, g_max=g, dig_kernel=dig_kernel, eri_block=256)
+            J, K = gpu_jk(b, D, dev)
+            assert maxabs(J, Jr) <= TOL and maxabs(K, Kr) <= TOL, g
+            J, K = gpu_jk(b, D, dev, precision=jk.JK_MIXED)
+            assert np.all(rel_frob(J, Jr) <= 1e-8) and np.all(rel_frob(K, Kr) <= 1e-8), g
+    finally:
+        for c, t in enumerate(old):
+            jk.jk_tune_set(c, **t)
+
+
 def test_cartesian_basis(dev):
     b = synth.random_basis(202, 4, 3, spherical=0)
     D = synth.random_densities(5, 4, b.nbf())
