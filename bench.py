@@ -51,7 +51,8 @@ def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".h", ".hip", ".cpp", ".py")):
+        # the J/K build's sources (the Laplace-cascade files do not change it)
+        if name.endswith((".h", ".hip", ".cpp", ".py")) and not name.startswith(("jk_gemm", "jk_laplace", "jk_remez")):
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -358,6 +359,7 @@ def main():
     ap.add_argument("--cpu-stride1", type=int, default=0,
                     help="oracle sample stride on one core (0: 1024 for the large workload, 128 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-cascade edge measurement")
     ap.add_argument("--serialized", action="store_true",
                     help="time only the profiled builds (launches one after another), for kernel-trace runs whose "
                          "per-kernel averages must match the roofline entry")
@@ -401,6 +403,8 @@ def main():
                                                  "digest_kernels_ms_per_step", "eri_kernels_frac_fp64_peak",
                                                  "basis_setup_s", "roofline", "mixed", "config")
                             if k in med}
+    if not args.no_laplace:
+        result["laplace_edge"] = laplace_edge_bench(w, dev, stream, max(2, args.steps // 5))
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on strided samples")
         st = args.cpu_stride or (64 if args.workload == "large" else 8)
@@ -409,6 +413,57 @@ def main():
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)
+
+
+def laplace_edge_bench(w, dev, stream, steps):
+    """One forward edge of the Laplace cascade (Sect. 2, the level-k loop)
+    on the workload's densities and orbitals: J/K build, Laplace-Fock
+    back-transform, next-level densities on a minimax grid for the
+    workload's denominator range; and the dense steps alone (matrix-core
+    FP64 products) against the FP64 MFMA peak."""
+    import numpy as np
+    import torch
+
+    from paper_2607_05622_amd import jk
+    orb = w.meta["orbitals"]
+    lo, hi = orb.gap_range()
+    ntau = 6
+    tau, wts, gerr = jk.jk_laplace_grid(ntau, lo, hi)
+    b = jk.JKBasis(w.basis)
+    try:
+        D = torch.tensor(w.D, dtype=torch.float64, device=dev)
+        C = torch.tensor(np.ascontiguousarray(orb.C), dtype=torch.float64, device=dev)
+        eps = torch.tensor(orb.eps, dtype=torch.float64, device=dev)
+        nd, n, nocc = D.shape[0], D.shape[1], orb.n_occ
+        nmo, nvir = C.shape[1], C.shape[1] - orb.n_occ
+        J, K, Rov, Dn = jk.jk_laplace_step(b.h, D, C, eps, nocc, tau, stream=stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            jk.jk_laplace_step(b.h, D, C, eps, nocc, tau, stream=stream)
+        ev[1].record(stream)
+        for _ in range(steps):
+            jk.jk_laplace_fock(C, nocc, J, K, Rov=Rov, want_f=False, stream=stream)
+            jk.jk_laplace_densities(C, eps, nocc, tau, Rov, Dn, stream=stream)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        edge_ms = ev[0].elapsed_time(ev[1]) / steps
+        dense_ms = ev[1].elapsed_time(ev[2]) / steps
+    finally:
+        b.close()
+    # algorithmic flops of the dense steps: (2J - K) C and its occupied-virtual
+    # block per density; U^k R and (U^k R) (V^k)^T per density and grid point
+    fock = nd * (2.0 * n * n * nmo + 2.0 * nocc * nvir * n)
+    dens = nd * ntau * (2.0 * n * nocc * nvir + 2.0 * n * n * nvir)
+    tf = (fock + dens) / (dense_ms * 1e-3) / 1e12
+    log(f"laplace edge: {edge_ms:.1f} ms per edge ({nd} densities -> {nd * ntau}), dense steps {dense_ms:.2f} ms "
+        f"({tf:.1f} TFLOP/s)")
+    return {"what": f"one forward edge of the level-k cascade: J/K of {nd} densities, back-transform, "
+                    f"{nd * ntau} next-level densities on a {ntau}-point minimax grid over [{lo:.3f}, {hi:.3f}]",
+            "grid_max_error": gerr, "ms_per_edge": edge_ms, "edges_per_s": 1e3 / edge_ms,
+            "dense_ms_per_edge": dense_ms, "dense_flops_per_edge": fock + dens, "dense_tflops": tf,
+            "dense_frac_fp64_mfma_peak": tf / 78.6, "steps": steps}
 
 
 def run_workload(args, name, steps, warmup, precision, dev, stream):

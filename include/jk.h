@@ -239,6 +239,64 @@ int jk_eri_tiles(jk_basis_t h, int32_t nq, const int32_t* shells, double* out);
 int jk_profile_enable(jk_basis_t h, int32_t on);
 int jk_profile_read(jk_basis_t h, int32_t kind, int32_t cls, double out[5]);
 
+/* ---- Laplace grids and the forward Laplace cascade (Sect. 2) ----------- */
+
+#define JK_LAPLACE_MAX_POINTS 64
+
+/* Minimax grid of Eq. (laplace): n nodes tau[k] and weights w[k] (host
+ * arrays of n) such that max |1/x - sum_k w[k] exp(-x tau[k])| over
+ * x in [xmin, xmax] is smallest (the best uniform approximation by an
+ * exponential sum; the paper's minimax grid paragraph of Sect. 2).  Found by
+ * the Remez exchange on [1, xmax/xmin] and scaled; *max_err (may be NULL)
+ * receives that largest error.  Host only, synchronous.  JK_EINVAL for n
+ * outside 1..JK_LAPLACE_MAX_POINTS or not 0 < xmin < xmax < inf;
+ * JK_EUNSUPPORTED when the exchange does not converge for that many points
+ * on that range ratio (fewer points do; the message says which case). */
+int jk_laplace_grid(int32_t n, double xmin, double xmax, double* tau, double* w, double* max_err);
+
+/* Omega-shifted weights of Eq. (eomshift): w_out[k] = w[k] exp(omega tau[k]),
+ * so that sum_k w_out[k] exp(-D tau[k]) approximates 1/(D - omega) wherever
+ * the grid approximates 1/(D - omega) (the grid must cover the shifted range
+ * [dmin - omega, dmax - omega]).  JK_EINVAL unless omega < dmin, the
+ * smallest denominator (the paper's validity condition). */
+int jk_laplace_shift(int32_t n, const double* tau, const double* w, double omega, double dmin, double* w_out);
+
+/* Level-k AO densities of Eqs. (scaledcoeff) and (aodensk): for every
+ * residual r < nr and grid point k < ntau,
+ *   D[r][k] = U^k R[r] (V^k)^T,  U^k = C_occ diag(exp(+eps_i tau_k)),
+ *                                V^k = C_vir diag(exp(-eps_a tau_k)).
+ * Device pointers: C [n][nocc + nvir] row-major (AO rows, MO columns, the
+ * nocc occupied first), eps [nocc + nvir], R [nr][nocc][nvir],
+ * D [nr][ntau][n][n] (overwritten); tau is a host array of ntau
+ * (1..JK_LAPLACE_MAX_POINTS).  Asynchronous on stream (a hipStream_t, NULL
+ * = default); scratch of ntau n (nocc + nvir) + nr n nvir doubles is taken
+ * and released on that stream.  JK_EINVAL for bad sizes or NULL pointers,
+ * JK_ENOMEM when the scratch cannot be allocated. */
+int jk_laplace_densities(int32_t n, int32_t nocc, int32_t nvir, const double* C, const double* eps, int32_t ntau,
+                         const double* tau, int32_t nr, const double* R, double* D, void* stream);
+
+/* Laplace-Fock back-transform of Eq. (laplacefock) for nd densities:
+ * F[x] = C^T (2 J[x] - K[x]) C ([nd][nocc + nvir][nocc + nvir]) and/or its
+ * occupied-virtual block Rov[x] = F[x][occ][vir] ([nd][nocc][nvir]), the
+ * residual that seeds the next level of the cascade (reading of the
+ * "occupied-virtual projection" of Eq. (aodensk)).  Device pointers, C as
+ * for jk_laplace_densities, J and K [nd][n][n] as jk_build writes them; F or
+ * Rov may be NULL (not both).  Asynchronous on stream; scratch of at most
+ * 64 n (n + nocc + nvir) doubles.  JK_EINVAL, JK_ENOMEM as above. */
+int jk_laplace_fock(int32_t n, int32_t nocc, int32_t nvir, const double* C, int32_t nd, const double* J,
+                    const double* K, double* F, double* Rov, void* stream);
+
+/* One forward edge of the level-k cascade (Algorithm ltao, the level-k
+ * loop): J and K of the nd level-(k-1) densities D (jk_build, into the
+ * caller's J and K), their back-transform's occupied-virtual blocks Rov
+ * ([nd][nocc][nvir]) and the level-k densities Dnext ([nd][ntau][n][n]) on
+ * the grid tau (host, ntau points), all on o->stream.  n = jk_nbf(h);
+ * o->want_j and o->want_k must be set.  Errors as jk_build and the two
+ * calls above. */
+int jk_laplace_step(jk_basis_t h, int32_t nd, const double* D, double* J, double* K, int32_t nocc, int32_t nvir,
+                    const double* C, const double* eps, int32_t ntau, const double* tau, double* Rov, double* Dnext,
+                    const jk_build_opts* o);
+
 #ifdef __cplusplus
 }
 #endif

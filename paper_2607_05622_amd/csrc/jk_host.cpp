@@ -171,6 +171,10 @@ constexpr int kFp32MaxL = 4;
 
 }  // namespace
 
+// Error recording for the other translation units of the library.
+int record_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+
 namespace {
 struct CachedPlan;
 void free_plan(CachedPlan* cp);

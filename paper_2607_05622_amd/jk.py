@@ -109,6 +109,19 @@ def load(path: str = LIB_PATH):
     lib.jk_profile_enable.restype = c_int
     lib.jk_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.jk_profile_read.restype = c_int
+    hd = ctypes.POINTER(ctypes.c_double)
+    i32, f64 = ctypes.c_int32, ctypes.c_double
+    lib.jk_laplace_grid.argtypes = [i32, f64, f64, hd, hd, hd]
+    lib.jk_laplace_grid.restype = c_int
+    lib.jk_laplace_shift.argtypes = [i32, hd, hd, f64, f64, hd]
+    lib.jk_laplace_shift.restype = c_int
+    lib.jk_laplace_densities.argtypes = [i32, i32, i32, dp, dp, i32, hd, i32, dp, dp, vp]
+    lib.jk_laplace_densities.restype = c_int
+    lib.jk_laplace_fock.argtypes = [i32, i32, i32, dp, i32, dp, dp, dp, dp, vp]
+    lib.jk_laplace_fock.restype = c_int
+    lib.jk_laplace_step.argtypes = [vp, i32, dp, dp, dp, i32, i32, dp, dp, i32, hd, dp, dp,
+                                    ctypes.POINTER(jk_build_opts)]
+    lib.jk_laplace_step.restype = c_int
     _lib = lib
     return lib
 
@@ -367,3 +380,93 @@ class JKBasis:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------ Laplace grids and cascade --
+
+def _hd(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def jk_laplace_grid(n: int, xmin: float, xmax: float):
+    """Minimax grid (tau, w, max_err) for 1/x on [xmin, xmax] (host arrays)."""
+    tau, w, err = np.zeros(n), np.zeros(n), ctypes.c_double()
+    _check(load().jk_laplace_grid(n, xmin, xmax, _hd(tau), _hd(w), ctypes.byref(err)))
+    return tau, w, err.value
+
+
+def jk_laplace_shift(tau, w, omega: float, dmin: float):
+    """Weights reweighted for 1/(D - omega)."""
+    tau, w = np.ascontiguousarray(tau, dtype=np.float64), np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros_like(w)
+    _check(load().jk_laplace_shift(len(tau), _hd(tau), _hd(w), omega, dmin, _hd(out)))
+    return out
+
+
+def _dev_mat(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 cuda tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _stream(s, dev):
+    import torch
+    s = s if s is not None else torch.cuda.current_stream(dev)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def jk_laplace_densities(C, eps, nocc: int, tau, R, D=None, stream=None):
+    """D[r, k] = U^k R[r] (V^k)^T for residuals R[nr, nocc, nvir] on the grid
+    tau (host); C[n, nmo] and eps[nmo] on the device."""
+    import torch
+    n, nmo = C.shape
+    nvir = nmo - nocc
+    nr = R.shape[0]
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    if D is None:
+        D = torch.empty((nr, len(tau), n, n), dtype=torch.float64, device=C.device)
+    _check(load().jk_laplace_densities(n, nocc, nvir, _dev_mat(C, (n, nmo), "C"), _dev_mat(eps, (nmo,), "eps"),
+                                       len(tau), _hd(tau), nr, _dev_mat(R, (nr, nocc, nvir), "R"),
+                                       _dev_mat(D, (nr, len(tau), n, n), "D"), _stream(stream, C.device)))
+    return D
+
+
+def jk_laplace_fock(C, nocc: int, J, K, F=None, Rov=None, want_f=True, want_r=True, stream=None):
+    """F = C^T (2J - K) C per density and its occupied-virtual block."""
+    import torch
+    n, nmo = C.shape
+    nvir = nmo - nocc
+    nd = J.shape[0]
+    if want_f and F is None:
+        F = torch.empty((nd, nmo, nmo), dtype=torch.float64, device=C.device)
+    if want_r and Rov is None:
+        Rov = torch.empty((nd, nocc, nvir), dtype=torch.float64, device=C.device)
+    _check(load().jk_laplace_fock(n, nocc, nvir, _dev_mat(C, (n, nmo), "C"), nd, _dev_mat(J, (nd, n, n), "J"),
+                                  _dev_mat(K, (nd, n, n), "K"),
+                                  _dev_mat(F, (nd, nmo, nmo), "F") if want_f else None,
+                                  _dev_mat(Rov, (nd, nocc, nvir), "Rov") if want_r else None,
+                                  _stream(stream, C.device)))
+    return F, Rov
+
+
+def jk_laplace_step(h, D, C, eps, nocc: int, tau, opts: jk_build_opts | None = None, stream=None):
+    """One forward edge of the cascade: returns (J, K, Rov, Dnext)."""
+    import torch
+    n = jk_nbf(h)
+    nd = D.shape[0]
+    nmo = C.shape[1]
+    nvir = nmo - nocc
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    J, K = torch.empty_like(D), torch.empty_like(D)
+    Rov = torch.empty((nd, nocc, nvir), dtype=torch.float64, device=D.device)
+    Dn = torch.empty((nd, len(tau), n, n), dtype=torch.float64, device=D.device)
+    o = opts if opts is not None else jk_default_opts()
+    o.stream = _stream(stream, D.device)
+    _check(load().jk_laplace_step(h, nd, _dev_ptr(D, n, "D"), _dev_ptr(J, n, "J"), _dev_ptr(K, n, "K"), nocc, nvir,
+                                  _dev_mat(C, (n, nmo), "C"), _dev_mat(eps, (nmo,), "eps"), len(tau), _hd(tau),
+                                  _dev_mat(Rov, (nd, nocc, nvir), "Rov"), _dev_mat(Dn, (nd, len(tau), n, n), "Dnext"),
+                                  ctypes.byref(o)))
+    return J, K, Rov, Dn
