@@ -232,21 +232,25 @@ def serve_bench(args):
         log(f"serve: molecule {i} resident ({bb.nbf()} AO)")
     o64 = jk.jk_default_opts()
     Dt = [torch.tensor(d, device=dev) for d in reqs_d]
-    # capacity of the plain form: mean service time over the stream
+    # capacity of the plain form: mean service time over the first requests
     for i in range(min(4, len(stream))):
         jk.jk_build(handles[stream[i]["mol"]].h, Dt[i], opts=o64)
     torch.cuda.synchronize()
+    ncap = min(len(stream), args.capacity_requests)
     t0 = time.perf_counter()
-    for i, r in enumerate(stream):
+    for i, r in enumerate(stream[:ncap]):
         jk.jk_build(handles[r["mol"]].h, Dt[i], opts=o64)
         if i % 50 == 49:
             torch.cuda.synchronize()
-            log(f"serve: capacity run {i + 1}/{len(stream)}")
+            log(f"serve: capacity run {i + 1}/{ncap}")
     torch.cuda.synchronize()
-    service = (time.perf_counter() - t0) / len(stream)
+    service = (time.perf_counter() - t0) / ncap
     capacity = 1.0 / service
     log(f"serve: one-at-a-time FP64 service {service * 1e3:.1f} ms/request")
-    srv = serve.JKServer(bases, n_slots=4, precision=jk.JK_MIXED, max_batch=16)
+    # one launch at a time in arrival order (requests sharing the GPU finish
+    # later than in turn), mixed precision, graph replays for lone requests,
+    # and batches only of small molecules' requests
+    srv = serve.JKServer(bases, n_slots=args.slots, precision=jk.JK_MIXED, max_batch=16, batch_nbf_max=256)
     srv.warm_graphs(max_nd=64, on_progress=lambda s, m: log(f"serve: graphs of slot {s} molecule {m} captured"))
     rates = [float(x) for x in args.rates.split(",")]
     phases = []
@@ -287,6 +291,8 @@ def serve_bench(args):
                                   f"{', '.join(str(r) for r in rates)} x the plain FP64 one-at-a-time capacity "
                                   f"({capacity:.2f} requests/s); value = mixed server builds/s at the highest rate"},
            "plain_fp64_service_ms": service * 1e3,
+           "server": {"slots": args.slots, "max_batch": 16, "batch_nbf_max": 256, "graphs": True,
+                      "capacity_requests": ncap},
            "speedup_vs_plain_fp64": top["speedup_vs_plain_fp64"],
            "per_rate": [{"rate": ph["rate_vs_plain_capacity"],
                          "server_builds_per_s": ph["server_mixed"]["builds_per_s"],
@@ -354,6 +360,9 @@ def main():
     ap.add_argument("--requests", type=int, default=500, help="requests per arrival rate (--serve)")
     ap.add_argument("--rates", default="0.25,0.5,1,1.5,2",
                     help="arrival rates as multiples of the FP64 one-at-a-time capacity (--serve)")
+    ap.add_argument("--slots", type=int, default=1, help="server launch slots (--serve)")
+    ap.add_argument("--capacity-requests", type=int, default=150,
+                    help="requests timed one at a time for the plain form's capacity (--serve)")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample stride on all cores (0: 64 for the large workload, 8 otherwise)")
     ap.add_argument("--cpu-stride1", type=int, default=0,

@@ -12,8 +12,9 @@ oldest waiting requests whose combined workspace fits its arena (admission by
 device memory) and launches them as one batched build (`jk_build_batch`), so
 requests that arrive while others run are folded into the next launch and
 overlap on the device with the other slots.  A lone request replays a HIP
-graph of its build (captured per slot, molecule and power-of-two density
-count) from fixed slot buffers.
+graph of its build (captured per slot, molecule and density-group count:
+8, 16, 32, 48 or 64 densities) from fixed slot buffers, so zero padding
+adds no digestion work.
 
 Latency of a request = completion (a HIP event on its slot's stream, read
 against an event recorded at the start of the run) minus its scheduled
@@ -56,11 +57,19 @@ class Request:
         return int(self.D.shape[0])
 
 
-def _pow2(n):
-    p = 1
-    while p < n:
-        p *= 2
-    return p
+def _bucket(nd):
+    """Density count a graph is captured for: the digestion works in groups
+    of 8 (up to 8 densities) or 16, so a request runs on the graph of its
+    group count and the zero padding adds no digestion work."""
+    return 8 if nd <= 8 else (nd + 15) // 16 * 16
+
+
+def _buckets(max_nd):
+    out, b = [], 8
+    while b <= max(8, max_nd):
+        out.append(b)
+        b = 16 if b == 8 else b + 16
+    return out
 
 
 @dataclass
@@ -77,12 +86,17 @@ class JKServer:
     """Serve J/K requests over resident molecules."""
 
     def __init__(self, bases, n_slots: int = 4, mem_budget: int | None = None, precision: int = jk.JK_MIXED,
-                 max_batch: int = 16, use_graphs: bool = True, graph_max_nd: int = 64, device="cuda:0"):
+                 max_batch: int = 16, use_graphs: bool = True, graph_max_nd: int = 64, batch_nbf_max: int | None = None,
+                 device="cuda:0"):
         self.dev = torch.device(device)
         self.handles = [jk.JKBasis(b) for b in bases]
         self.nbf = [h.nbf for h in self.handles]
         self.opts = jk.jk_default_opts(precision=precision)
         self.max_batch = max_batch
+        # requests on molecules above this size always launch alone (their
+        # builds fill the GPU by themselves; batching would only hold back the
+        # earlier requests of a batch until its end)
+        self.batch_nbf_max = batch_nbf_max
         self.use_graphs = use_graphs
         self.graph_max_nd = graph_max_nd
         if mem_budget is None:
@@ -114,6 +128,9 @@ class JKServer:
         n = self.nbf[mol]
         return jk.jk_workspace_bytes(self.handles[mol].h, nd_bucket, self.opts) + 3 * nd_bucket * n * n * 8
 
+    def _batchable(self, req) -> bool:
+        return self.batch_nbf_max is None or self.nbf[req.mol] <= self.batch_nbf_max
+
     def fits_alone(self, req) -> bool:
         return self.single_bytes(req.mol, req.nd) <= self.slot_bytes
 
@@ -140,15 +157,13 @@ class JKServer:
         return slot.graphs[key]
 
     def warm_graphs(self, mols=None, max_nd=None, on_progress=None):
-        """Capture the graphs of every (slot, molecule, power-of-two nd)."""
+        """Capture the graphs of every (slot, molecule, density bucket)."""
         mols = range(len(self.handles)) if mols is None else mols
         max_nd = max_nd or self.graph_max_nd
         for si, slot in enumerate(self.slots):
             for m in mols:
-                ndb = 1
-                while ndb <= max_nd:
+                for ndb in _buckets(max_nd):
                     self._graph(slot, m, ndb)
-                    ndb *= 2
                 if on_progress:
                     on_progress(si, m)
         torch.cuda.synchronize(self.dev)
@@ -163,7 +178,7 @@ class JKServer:
         with torch.cuda.stream(s):
             if len(reqs) == 1 and self.use_graphs and reqs[0].nd <= self.graph_max_nd:
                 r = reqs[0]
-                ndb = _pow2(r.nd)
+                ndb = _bucket(r.nd)
                 gr = self._graph(slot, r.mol, ndb)
                 if gr is not None:
                     g, D, J, K = gr
@@ -231,7 +246,7 @@ class JKServer:
                     batch = [queue[0]]
                     est = self.single_bytes(queue[0].mol, queue[0].nd)
                     for r in queue[1:]:
-                        if len(batch) >= self.max_batch:
+                        if len(batch) >= self.max_batch or not self._batchable(batch[0]) or not self._batchable(r):
                             break
                         e = self.single_bytes(r.mol, r.nd)
                         if est + e > self.slot_bytes:
