@@ -200,10 +200,18 @@ def cpu_baseline(w, stride, stride1, results):
             dk2 += np.sum((K[sl] - Kb) ** 2, axis=(1, 2))
             rj2 += np.sum(Jb ** 2, axis=(1, 2))
             rk2 += np.sum(Kb ** 2, axis=(1, 2))
+        # per density: the blocks' error norm over the whole matrix's norm (the
+        # 1e-8 bar is on whole matrices; a block's own norm can be tiny), and,
+        # stricter, over the blocks' own norm
+        wj2, wk2 = np.sum(J ** 2, axis=(1, 2)), np.sum(K ** 2, axis=(1, 2))
         acc[name] = {"max_abs_dJ": ej, "max_abs_dK": ek,
-                     "max_rel_frob_dJ": float(np.max(np.sqrt(dj2 / rj2))),
-                     "max_rel_frob_dK": float(np.max(np.sqrt(dk2 / rk2)))}
-    out["accuracy_vs_oracle"] = {"blocks": len(blocks), "per_density_rel_frob_over_blocks": True, **acc}
+                     "max_rel_frob_dJ": float(np.max(np.sqrt(dj2 / wj2))),
+                     "max_rel_frob_dK": float(np.max(np.sqrt(dk2 / wk2))),
+                     "max_rel_frob_dJ_of_blocks": float(np.max(np.sqrt(dj2 / rj2))),
+                     "max_rel_frob_dK_of_blocks": float(np.max(np.sqrt(dk2 / rk2)))}
+    out["accuracy_vs_oracle"] = {"blocks": len(blocks),
+                                 "rel_frob": "per density, the blocks' error norm over the whole matrix's norm; "
+                                             "_of_blocks: over the blocks' own norm", **acc}
     return out
 
 
