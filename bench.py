@@ -64,10 +64,19 @@ def rocprof_name(kernel, g16=True):
     parts = kernel.split("_")
     tag = parts[-1]
     r = "float" if "fp32" in parts else "double"
+    g = "true" if g16 else "false"
+    la = ", ".join(tag)
     if kernel.startswith("eri_tile"):
         return f"void jk::k_eri_tile<jk::Eri{tag}<{r}>, {r}>(jk::EriTileArgs)"
-    return (f"void jk::k_digest_{parts[1]}<{tag[0]}, {tag[1]}, {tag[2]}, {tag[3]}, {r}, "
-            f"{'true' if g16 else 'false'}>(jk::DigestArgs)")
+    if parts[1] == "c":   # pass C (last template argument: the one-pass form, off by default)
+        return f"void jk::k_digest_c<{la}, {r}, {g}, false>(jk::DigestArgs)"
+    if r == "double" and tag not in PASS_D_16x16:   # FP64 pass D on 4 x 4 blocks
+        return f"void jk::k_digest_d4<{la}, {g}>(jk::DigestArgs)"
+    return f"void jk::k_digest_d<{la}, {r}, {g}>(jk::DigestArgs)"
+
+
+# classes whose FP64 pass D keeps 16 x 16 tiles (the library's dig_d4 table)
+PASS_D_16x16 = {"1111", "2111", "2121", "2210", "2211", "2222"}
 
 
 WORKLOAD_TAG = {"tiny": "tiny28", "medium": "medium312", "large": "large620"}

@@ -59,6 +59,9 @@ hipError_t launch_digest_tpl(const DigestArgs& a, hipStream_t s, int pass, int g
     if (pass == 0) {
         if (g16) hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, true>), grid, dim3(a.skip_t ? 128 : 192), 0, s, a);
         else hipLaunchKernelGGL((k_digest_c<la, lb, lc, ld, TT, false>), grid, dim3(128), 0, s, a);
+    } else if constexpr (sizeof(TT) == 8 && dig_d4(la, lb, lc, ld)) {
+        if (g16) hipLaunchKernelGGL((k_digest_d4<la, lb, lc, ld, true>), grid, dim3(a.skip_t ? 64 : 128), 0, s, a);
+        else hipLaunchKernelGGL((k_digest_d4<la, lb, lc, ld, false>), grid, dim3(64), 0, s, a);
     } else {
         if (g16) hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, true>), grid, dim3(a.skip_t ? 64 : 128), 0, s, a);
         else hipLaunchKernelGGL((k_digest_d<la, lb, lc, ld, TT, false>), grid, dim3(64), 0, s, a);

@@ -29,7 +29,9 @@
 // K_bc) keep their sums in the MFMA accumulators until the run of equal c
 // ends; J_cd is written per quartet.  Pass C walks that order and also
 // writes each tile, quartet-major, at its position in the (d, c) order;
-// pass D walks that copy in runs of equal d for K_ad and K_bd.
+// pass D walks that copy in runs of equal d for K_ad and K_bd, for most
+// classes of the FP64 tier on 4 x 4 matrix-core blocks (k_digest_d4), whose
+// 4-row output tiles fit pass D's short outputs.
 #pragma once
 
 #include "jk_device.h"
@@ -618,6 +620,141 @@ void k_digest_d(DigestArgs a) {
                     row = fb + mo / ND;
                     col = fd + mo % ND;
                 });
+        }
+        p += n;
+        lds_barrier();
+    }
+}
+
+// v_mfma_f64_4x4x4f64: four independent 4 x 4 products with k-depth 4; it
+// issues every 16 cycles, a quarter of the 16 x 16 x 4 form, at the same
+// FP64 rate.  Lane l = 16 q + 4 b + r works on block b: it supplies A[r][q]
+// and B[q][r] and holds C[q][r] (probed).  Below, u = 4 q + r.
+struct Mfma4 {
+    static __device__ __forceinline__ int block(int lane) { return (lane >> 2) & 3; }
+    static __device__ __forceinline__ int u(int lane) { return ((lane >> 4) << 2) | (lane & 3); }
+    static __device__ __forceinline__ double step(double a, double b, double c) {
+        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int arow(int u) { return u & 3; }
+    static __device__ __forceinline__ int ak(int u) { return u >> 2; }
+    static __device__ __forceinline__ int bk(int u) { return u >> 2; }
+    static __device__ __forceinline__ int bcol(int u) { return u & 3; }
+    static __device__ __forceinline__ int crow(int u) { return u >> 2; }
+    static __device__ __forceinline__ int ccol(int u) { return u & 3; }
+};
+
+// Pass D on 4 x 4 blocks (FP64 tier): the same contractions as k_digest_d,
+// with output tiles of 4 rows instead of 16.  The outputs of pass D (K_ad:
+// NA ND rows, K_bd: NB ND rows) are short for most classes, so 16-row tiles
+// leave most of each matrix-core operation idle; 4-row tiles waste at most
+// three rows.  The four blocks of a wave take four densities each (16-density
+// groups) or, with 8-density groups, the D contraction (blocks 0, 1) and the
+// D^T one (blocks 2, 3).
+template <int LA, int LB, int LC, int LD, bool G16>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(DigShape<LA, LB, LC, LD>::WAVES_D)))
+void k_digest_d4(DigestArgs a) {
+    using S = DigShape<LA, LB, LC, LD>;
+    constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND, NF = S::NF, NCD = S::NCD;
+    constexpr int QB = S::QB_D, QBP = S::QBP_D;
+    constexpr int T5 = (NA * ND + 3) / 4, T6 = (NB * ND + 3) / 4, NT = T5 + T6;   // 4-row output tiles
+    __shared__ double sT[NF * QBP];
+    __shared__ int sV[QB];
+
+    int p0 = 0, plen = 0, grp = 0;
+    const DigItem* itp = dig_task(a, p0, plen, grp);
+    if (!itp) return;
+    const DigItem it = *itp;
+    const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+    const int blk = Mfma4::block(lane), u = Mfma4::u(lane);
+    const int arow = Mfma4::arow(u), ak = Mfma4::ak(u), bk = Mfma4::bk(u);
+    const int crow = Mfma4::crow(u);
+    // density of the lane's B column and of its output column, and the form
+    const int xb = G16 ? grp * 16 + 4 * blk + Mfma4::bcol(u) : grp * 8 + 4 * (blk & 1) + Mfma4::bcol(u);
+    const int xc = G16 ? grp * 16 + 4 * blk + Mfma4::ccol(u) : grp * 8 + 4 * (blk & 1) + Mfma4::ccol(u);
+    const bool tr = G16 ? wave == 1 : blk >= 2;
+    const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
+    const DigLane<double> L(m, xb, tr);
+    double* const out = tr ? m.KT : m.K;
+    const PairInfo& P = m.pairs[it.bra];
+    const int fa = P.fa, fb = P.fb;
+    const gptr<const double> cp = glob(static_cast<const double*>(a.dcopy)) + it.tile_off;
+    const long long qrel = it.blk0 - it.chunk_q0;
+    const gptr<const long long> kin = glob(reinterpret_cast<const long long*>(it.kin)) + it.blk0;
+
+    // tile row of this lane's A operand: K_ad rows (i, l), K_bd rows (j, l)
+    int frow[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        frow[t] = 0;
+        if (t < T5) {
+            const int r = 4 * t + arow;
+            if (r < NA * ND) frow[t] = (r / ND) * NB * NCD + r % ND;
+        } else {
+            const int r = 4 * (t - T5) + arow;
+            if (r < NB * ND) frow[t] = (r / ND) * NCD + r % ND;
+        }
+    }
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+
+    const int pend = p0 + plen;
+    for (int p = p0; p < pend;) {
+        int2 kv;
+        bool more;
+        const int n = dig_chunk<QB>(kin, p, pend, lane, 16, kv, more);
+        const int fd = __shfl(kv.y >> 16, 0), fc0 = __shfl(kv.y & 0xffff, 0);
+        if (wave == 0 && lane < QB) sV[lane] = lane < n ? kv.y & 0xffff : fc0;
+        for (int base = 0; base < NF * QB; base += static_cast<int>(blockDim.x)) {
+            const int idx = base + static_cast<int>(threadIdx.x);
+            const int qb = idx / NF, f = idx - (idx / NF) * NF;
+            double t = 0.0;
+            if (idx < NF * QB && p + qb < pend) t = cp[(qrel + p + qb) * NF + f];
+            if (idx < NF * QB) sT[f * QBP + qb] = qb < n ? t : 0.0;
+        }
+        lds_barrier();
+        const int nquad = (n + 3) >> 2;
+        for (int s = 0; s < nquad; ++s) {
+            const int qa = 4 * s + ak;                  // A's quartet (k index)
+            const long long V0 = sV[4 * s + bk];        // B's quartet: its c functions
+            double b5[NB * NC], b6[NA * NC];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) b5[j * NC + k] = L.dk(fb + j, V0 + k);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) b6[i * NC + k] = L.dk(fa + i, V0 + k);
+            // K_ad: contraction over (j, k)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+#pragma unroll
+                    for (int t = 0; t < T5; ++t)
+                        acc[t] = Mfma4::step(sT[(frow[t] + j * NCD + k * ND) * QBP + qa], b5[j * NC + k], acc[t]);
+            // K_bd: contraction over (i, k)
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+#pragma unroll
+                    for (int t = T5; t < NT; ++t)
+                        acc[t] = Mfma4::step(sT[(frow[t] + i * NB * NCD + k * ND) * QBP + qa], b6[i * NC + k], acc[t]);
+        }
+        if (!more) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bool ad = t < T5;
+                const int r = 4 * (ad ? t : t - T5) + crow;
+                if (r < (ad ? NA * ND : NB * ND) && xc < m.nd) {
+                    const long long row = (ad ? fa : fb) + r / ND, col = fd + r % ND;
+                    gadd(out + (row * m.nc + col) * L.ndp + xc, acc[t]);
+                }
+                acc[t] = 0.0;
+            }
         }
         p += n;
         lds_barrier();

@@ -24,7 +24,9 @@ def test_more_than_one_gpu_is_refused():
 def test_rocprof_names():
     assert bench.rocprof_name("eri_tile_2221") == "void jk::k_eri_tile<jk::Eri2221<double>, double>(jk::EriTileArgs)"
     assert bench.rocprof_name("eri_tile_fp32_1010") == "void jk::k_eri_tile<jk::Eri1010<float>, float>(jk::EriTileArgs)"
-    assert bench.rocprof_name("digest_c_2110") == "void jk::k_digest_c<2, 1, 1, 0, double, true>(jk::DigestArgs)"
+    assert bench.rocprof_name("digest_c_2110") == "void jk::k_digest_c<2, 1, 1, 0, double, true, false>(jk::DigestArgs)"
+    assert bench.rocprof_name("digest_d_2110") == "void jk::k_digest_d4<2, 1, 1, 0, true>(jk::DigestArgs)"
+    assert bench.rocprof_name("digest_d_2222") == "void jk::k_digest_d<2, 2, 2, 2, double, true>(jk::DigestArgs)"
     assert (bench.rocprof_name("digest_d_fp32_2221", g16=False)
             == "void jk::k_digest_d<2, 2, 2, 1, float, false>(jk::DigestArgs)")
 
