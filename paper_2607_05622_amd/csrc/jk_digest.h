@@ -221,6 +221,24 @@ __device__ __forceinline__ int dig_chunk(gptr<const long long> kin, int p, int p
     return more ? QB : n;
 }
 
+// v_mfma_f64_4x4x4f64: four independent 4 x 4 products with k-depth 4; it
+// issues every 16 cycles, a quarter of the 16 x 16 x 4 form, at the same
+// FP64 rate.  Lane l = 16 q + 4 b + r works on block b: it supplies A[r][q]
+// and B[q][r] and holds C[q][r] (probed).  Below, u = 4 q + r.
+struct Mfma4 {
+    static __device__ __forceinline__ int block(int lane) { return (lane >> 2) & 3; }
+    static __device__ __forceinline__ int u(int lane) { return ((lane >> 4) << 2) | (lane & 3); }
+    static __device__ __forceinline__ double step(double a, double b, double c) {
+        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int arow(int u) { return u & 3; }
+    static __device__ __forceinline__ int ak(int u) { return u >> 2; }
+    static __device__ __forceinline__ int bk(int u) { return u >> 2; }
+    static __device__ __forceinline__ int bcol(int u) { return u & 3; }
+    static __device__ __forceinline__ int crow(int u) { return u >> 2; }
+    static __device__ __forceinline__ int ccol(int u) { return u & 3; }
+};
+
 // K_ad += I D_bc and K_bd += I D_ac for the n quartets of a staged chunk
 // whose ket shell c (first function fc) is shared and whose d functions
 // start at sV[q]: output rows (q, i, l) and (q, j, l), contraction over
@@ -331,6 +349,28 @@ void k_digest_c(DigestArgs a) {
     const MolDesc m = load_mol(a.mols, a.mol0, it.mol);
     const DigLane<R> L(m, G16 ? grp * 16 + c16 : grp * 8 + (c16 & 7), G16 ? wave == 2 : c16 >= 8);
     const long long nc = m.nc;
+    // FP64 tier: the K waves on 4 x 4 blocks (4-row tiles of K_ac and K_bc),
+    // with their own lane map: four densities per block, or with 8-density
+    // groups the D contraction on blocks 0, 1 and the D^T one on 2, 3
+    constexpr bool K4 = !OP && sizeof(TT) == 8 && dig_c4(LA, LB, LC, LD);
+    constexpr int T3 = (NA * NC + 3) / 4, T4 = (NB * NC + 3) / 4, NT4 = K4 ? T3 + T4 : 1;
+    const int blk4 = Mfma4::block(lane), u4 = Mfma4::u(lane);
+    const int xb4 = G16 ? grp * 16 + 4 * blk4 + Mfma4::bcol(u4) : grp * 8 + 4 * (blk4 & 1) + Mfma4::bcol(u4);
+    const int xc4 = G16 ? grp * 16 + 4 * blk4 + Mfma4::ccol(u4) : grp * 8 + 4 * (blk4 & 1) + Mfma4::ccol(u4);
+    const bool tr4 = G16 ? wave == 2 : blk4 >= 2;
+    const DigLane<R> L4(m, K4 ? xb4 : 0, K4 && tr4);
+    int frow4[NT4];
+    double acc4[NT4];
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) {
+        frow4[t] = 0;
+        acc4[t] = 0.0;
+        if (K4 && wave != 0) {
+            const int r = 4 * (t < T3 ? t : t - T3) + Mfma4::arow(u4);
+            if (t < T3 && r < NA * NC) frow4[t] = (r / NC) * NB * NCD + (r % NC) * ND;
+            if (t >= T3 && r < NB * NC) frow4[t] = (r / NC) * NCD + (r % NC) * ND;
+        }
+    }
     const PairInfo& P = m.pairs[it.bra];
     const int fa = P.fa, fb = P.fb, sa = P.sa, sb = P.sb;
     const gptr<const TT> tile = glob(static_cast<const TT*>(a.tiles)) + it.tile_off;
@@ -445,6 +485,48 @@ void k_digest_c(DigestArgs a) {
                             gadd(m.J + ((fc + k) * nc + sV[qo] + l) * L.ndp + L.x, v);
                         }
                     }
+                }
+            }
+        } else if (K4 && a.want_k) {
+            const int ak = Mfma4::ak(u4), bk = Mfma4::bk(u4), crow = Mfma4::crow(u4);
+            for (int s = 0; s < nquad; ++s) {
+                const int qa = 4 * s + ak;                  // A's quartet (k index)
+                const long long V0 = sV[4 * s + bk];        // B's quartet: its d functions
+                R b3[NB * ND], b4[NA * ND];
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) b3[j * ND + l] = L4.dk(fb + j, V0 + l);
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) b4[i * ND + l] = L4.dk(fa + i, V0 + l);
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l)
+#pragma unroll
+                        for (int t = 0; t < T3; ++t)
+                            acc4[t] = Mfma4::step(sT[(frow4[t] + j * NCD + l) * QBP + qa], b3[j * ND + l], acc4[t]);
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l)
+#pragma unroll
+                        for (int t = T3; t < NT4; ++t)
+                            acc4[t] = Mfma4::step(sT[(frow4[t] + i * NB * NCD + l) * QBP + qa], b4[i * ND + l], acc4[t]);
+            }
+            if (!more) {
+                double* const out = tr4 ? m.KT : m.K;
+#pragma unroll
+                for (int t = 0; t < NT4; ++t) {
+                    const bool ac = t < T3;
+                    const int r = 4 * (ac ? t : t - T3) + crow;
+                    if (r < (ac ? NA * NC : NB * NC) && xc4 < m.nd) {
+                        const long long row = (ac ? fa : fb) + r / NC, col = fc + r % NC;
+                        gadd(out + (row * nc + col) * L4.ndp + xc4, acc4[t]);
+                    }
+                    acc4[t] = 0.0;
                 }
             }
         } else if (a.want_k) {
@@ -625,24 +707,6 @@ void k_digest_d(DigestArgs a) {
         lds_barrier();
     }
 }
-
-// v_mfma_f64_4x4x4f64: four independent 4 x 4 products with k-depth 4; it
-// issues every 16 cycles, a quarter of the 16 x 16 x 4 form, at the same
-// FP64 rate.  Lane l = 16 q + 4 b + r works on block b: it supplies A[r][q]
-// and B[q][r] and holds C[q][r] (probed).  Below, u = 4 q + r.
-struct Mfma4 {
-    static __device__ __forceinline__ int block(int lane) { return (lane >> 2) & 3; }
-    static __device__ __forceinline__ int u(int lane) { return ((lane >> 4) << 2) | (lane & 3); }
-    static __device__ __forceinline__ double step(double a, double b, double c) {
-        return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int arow(int u) { return u & 3; }
-    static __device__ __forceinline__ int ak(int u) { return u >> 2; }
-    static __device__ __forceinline__ int bk(int u) { return u >> 2; }
-    static __device__ __forceinline__ int bcol(int u) { return u & 3; }
-    static __device__ __forceinline__ int crow(int u) { return u >> 2; }
-    static __device__ __forceinline__ int ccol(int u) { return u & 3; }
-};
 
 // Pass D on 4 x 4 blocks (FP64 tier): the same contractions as k_digest_d,
 // with output tiles of 4 rows instead of 16.  The outputs of pass D (K_ad:

@@ -101,4 +101,14 @@ __host__ __device__ constexpr bool dig_d4(int la, int lb, int lc, int ld) {
     return !(t == 1111 || t == 2111 || t == 2121 || t == 2210 || t == 2211 || t == 2222);
 }
 
+// The K waves of pass C (FP64 tier) on 4 x 4 matrix-core blocks for class
+// (la lb | lc ld): timed per class on the 620-AO workload, where pass C took
+// 0.71-0.95 of its 16 x 16 time for these seven classes; the others ran at
+// 0.97-1.42 of it (their longer K rows fill 16-row tiles, and the extra
+// accumulators cost registers).
+__host__ __device__ constexpr bool dig_c4(int la, int lb, int lc, int ld) {
+    const int t = la * 1000 + lb * 100 + lc * 10 + ld;
+    return t == 0 || t == 1000 || t == 1010 || t == 1100 || t == 2000 || t == 2010 || t == 2011;
+}
+
 }  // namespace jk
