@@ -102,8 +102,14 @@ int jk_create_basis(const jk_basis_desc* d, jk_basis_t* out);
 /* Number of basis functions n of the D/J/K matrices (pure or Cartesian). */
 int jk_nbf(jk_basis_t h);
 
-/* J and K for nd densities.  D, J, K are device pointers to row-major
- * [nd][n][n] FP64 arrays (n = jk_nbf); J and K are overwritten.  The caller
+/* J and K for nd densities (Eq. (jkbuild), Sect. 2.2):
+ *   J[x][m][n] = sum_{l,s} (mn|ls) D[x][l][s],  K[x][m][n] = sum_{l,s} (ml|ns) D[x][l][s],
+ * bare builds (no 1/2, no 2J - K; the notation paragraph of Sect. 2) for
+ * generally non-symmetric D, which is used whole for K (Sect. 2.4).  The
+ * only approximation is the Schwarz and density screen at o->schwarz_tol
+ * (and, for JK_MIXED, the FP32 tier below o->fp32_bound; Sect. 3).  D, J, K
+ * are device pointers to row-major [nd][n][n] FP64 arrays (n = jk_nbf); J and
+ * K are overwritten.  The caller
  * owns D, J, K and the stream; D must stay valid, and J/K untouched, until
  * the stream has passed the call.  Asynchronous on o->stream.  Either output
  * may be NULL when the matching want_ flag is 0.  Re-entrant: one handle may
@@ -133,14 +139,18 @@ size_t jk_workspace_bytes(jk_basis_t h, int32_t nd, const jk_build_opts* o);
 int jk_build_noalloc(jk_basis_t h, int32_t nd, const double* D, double* J, double* K,
                      const jk_build_opts* o);
 
-/* Builds for several molecules at once: nmol handles (same device), density
- * counts nd[i] and device pointers D[i], J[i], K[i] (host arrays of nmol
- * entries; matrices as in jk_build).  For every shell-quartet class and
- * precision tier a single integral launch and a single digestion launch
- * cover all molecules: a work list of (molecule, class, tier, tile) items
- * walked by grid-stride blocks, so uneven molecules share the GPU.  Results
- * are those of nmol separate jk_build calls.  Asynchronous on o->stream;
- * workspace from jk_batch_workspace_bytes or stream-ordered allocation. */
+/* Builds for several molecules at once (Eq. (jkbuild) per molecule; the
+ * paper launches only the realized class buckets, Sect. 3, "DAG-driven,
+ * spill-bounded GPU chunking"): nmol handles (same device), density counts
+ * nd[i] and device pointers D[i], J[i], K[i] (host arrays of nmol entries;
+ * matrices as in jk_build).  For every shell-quartet class and precision
+ * tier, an integral launch and the two digestion launches (passes over runs
+ * of equal ket shell c and d) each walk a work list of (molecule, tile)
+ * items of all molecules, so uneven molecules share the GPU; a class whose
+ * tiles exceed the 2 GB work buffer is split into several such launches.
+ * There is no single persistent launch over all classes.  Results are those
+ * of nmol separate jk_build calls.  Asynchronous on o->stream; workspace from
+ * jk_batch_workspace_bytes or stream-ordered allocation. */
 int jk_build_batch(int32_t nmol, const jk_basis_t* h, const int32_t* nd, const double* const* D,
                    double* const* J, double* const* K, const jk_build_opts* o);
 size_t jk_batch_workspace_bytes(int32_t nmol, const jk_basis_t* h, const int32_t* nd,
