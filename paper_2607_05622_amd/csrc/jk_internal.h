@@ -82,13 +82,14 @@ __host__ __device__ constexpr int dig_qb_d(int la, int lb, int lc, int ld, int n
 
 // Minimum waves per SIMD the digestion kernels of class (la lb | lc ld) are
 // compiled for (pass C; pass D uses 3): the register budget that trades
-// spills against latency hiding, chosen by timing each class on the 312-AO
-// workload at 1 to 4.
+// spills against latency hiding, chosen by timing each class of pass C on
+// the 620-AO workload (40 densities) at 1 to 4 (e.g. (dd|dp): 54.7 ms at 1,
+// 29.4 ms at 3 per build).
 __host__ __device__ constexpr int dig_waves_c(int la, int lb, int lc, int ld) {
     const int t = la * 1000 + lb * 100 + lc * 10 + ld;
-    return (t == 1111 || t == 2221) ? 1
-           : (t == 2020 || t == 2111 || t == 2120 || t == 2121 || t == 2211) ? 3
-           : (t == 1110 || t == 2000) ? 4
+    return (t == 2100) ? 1
+           : (t == 2120 || t == 2121 || t == 2211 || t == 2221 || t == 2222) ? 3
+           : (t == 1000 || t == 1110 || t == 2020) ? 4
            : 2;
 }
 
