@@ -533,3 +533,19 @@ def random_densities(seed: int, nd: int, n: int, scale: float = 0.1,
     if symmetric:
         D = 0.5 * (D + D.transpose(0, 2, 1))
     return D
+
+
+def random_factors(seed: int, nd: int, n: int, r: int, scale: float = 0.3):
+    """Seeded left and right factors U, V [nd][n][r] of densities D = U V^T
+    (transition-density-like: rank r, not symmetric)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U = rng.normal(size=(nd, n, r)) * scale
+    V = rng.normal(size=(nd, n, r)) * scale
+    return U, V
+
+
+def random_symmetric_stack(seed: int, nvec: int, n: int, scale: float = 0.2) -> np.ndarray:
+    """Seeded symmetric matrices [nvec][n][n] (stand-ins for a factor's rows)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = rng.normal(size=(nvec, n, n)) * scale
+    return 0.5 * (B + B.transpose(0, 2, 1))
