@@ -307,6 +307,52 @@ int jk_laplace_step(jk_basis_t h, int32_t nd, const double* D, double* J, double
                     const double* C, const double* eps, int32_t ntau, const double* tau, double* Rov, double* Dnext,
                     const jk_build_opts* o);
 
+/* ---------------------------------------------------------------------
+ * Cholesky-factor (CD) J/K (Eqs. (cdfact), (cdj), (cdk), (cdknonsym),
+ * Sect. 3): the two-electron operator as (mn|ls) ~ sum_Q B_Q[m][n] B_Q[l][s],
+ * and J and K read off the factor by dense products.
+ * ------------------------------------------------------------------- */
+
+#define JK_CD_MAX_VECTORS 65535
+
+/* The factor of Eq. (cdfact) by pivoted Cholesky.  The operator is the
+ * matrix of (mn|ls) over the basis function pairs m >= n (user basis), with
+ * the entries of shell quartets whose Schwarz factors give
+ * Q_ab Q_cd < screen_tol set to zero: the column-fill screen of the passage
+ * on the positive semidefiniteness of the CD operator, which recommends
+ * screen_tol = 0.01 delta.  Each step takes as pivot the largest remaining
+ * diagonal (among diagonals within a relative 1e-10 of it, the lowest pair
+ * index m (m + 1) / 2 + n) and adds one vector; the factor is complete when
+ * the largest remaining diagonal is <= delta, so every entry of the
+ * operator minus B^T B is at most delta in size.  The operator is held as
+ * a pool of (number of significant pairs)^2 doubles during the call and
+ * released before it returns.
+ *
+ * B: device, [max_vectors][n][n] (n = jk_nbf(h)); its first *nvec_out
+ * matrices are overwritten with the symmetric B_Q, the rest untouched.
+ * pivots: device int32 [max_vectors] or NULL: the pair index of each
+ * vector's pivot.  Runs on stream (a hipStream_t, NULL = default) and
+ * returns when the factor is complete.  JK_EINVAL for bad arguments
+ * (delta <= 0, screen_tol < 0, max_vectors outside 0..JK_CD_MAX_VECTORS);
+ * JK_ENOMEM when the pool does not fit in free device memory or more than
+ * max_vectors vectors are needed (then *nvec_out = max_vectors and B is
+ * not written). */
+int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vectors, double* B, int32_t* pivots,
+                 int32_t* nvec_out, void* stream);
+
+/* J and K of nd densities D[x] = U[x] V[x]^T from a factor B (Eq. (cdj) for
+ * J; Eq. (cdknonsym) for K, Eq. (cdk) being the case U = V):
+ *   J[x] = sum_Q B_Q gamma_Q[x],  gamma_Q[x] = sum_ls B_Q[l][s] D[x][l][s]
+ *   K[x] = sum_Q (B_Q U[x]) (B_Q V[x])^T
+ * Device pointers: B [nvec][nf][nf] symmetric (as jk_cd_factor writes it),
+ * U and V [nd][nf][r] row-major, J and K [nd][nf][nf] (overwritten; either
+ * may be NULL, not both).  Asynchronous on stream; scratch of
+ * nd nf^2 + 2 nf nvec r + O(nf^2 + nvec nd) doubles is taken and released
+ * on it.  JK_EINVAL for bad sizes or NULL inputs, JK_ENOMEM when the
+ * scratch cannot be allocated. */
+int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, const double* U, const double* V,
+             double* J, double* K, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,9 +109,9 @@ def cd_jk(Bf: np.ndarray, U: np.ndarray, V: np.ndarray):
     K = np.zeros((nd, n, n))
     for x in range(nd):
         D = U[x] @ V[x].T
-        gamma = np.einsum("qls,ls->q", Bf, D)
-        J[x] = np.einsum("q,qmn->mn", gamma, Bf)
+        gamma = np.einsum("qls,ls->q", Bf, D, optimize=True)
+        J[x] = np.einsum("q,qmn->mn", gamma, Bf, optimize=True)
         BU = Bf @ U[x]      # [nvec][n][r]
         BV = Bf @ V[x]
-        K[x] = np.einsum("qmi,qni->mn", BU, BV)
+        K[x] = np.einsum("qmi,qni->mn", BU, BV, optimize=True)
     return J, K

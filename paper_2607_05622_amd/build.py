@@ -23,7 +23,8 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 NCLASS = 21
-HOST_SOURCES = ["jk_host", "jk_laplace", "jk_remez"]
+HOST_SOURCES = ["jk_host", "jk_laplace", "jk_remez", "jk_cd"]
+DEVICE_SOURCES = ["jk_kernels", "jk_gemm", "jk_cd"]
 
 # no packed FP32 instructions anywhere in device code
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -54,8 +55,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for n in range(NCLASS):
         steps.append(dev + [f"-DJK_CLASS_INDEX={n}", "-c", os.path.join(CSRC, "jk_class.hip"),
                             "-o", os.path.join(OBJ, f"jk_class_{n}.o")])
-    steps.append(dev + ["-c", os.path.join(CSRC, "jk_kernels.hip"), "-o", os.path.join(OBJ, "jk_kernels.o")])
-    steps.append(dev + ["-c", os.path.join(CSRC, "jk_gemm.hip"), "-o", os.path.join(OBJ, "jk_gemm.o")])
+    for src in DEVICE_SOURCES:
+        steps.append(dev + ["-c", os.path.join(CSRC, src + ".hip"), "-o", os.path.join(OBJ, src + "_dev.o")])
     for host in HOST_SOURCES:
         steps.append([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-x", "c++", "-c",
                       os.path.join(CSRC, host + ".cpp"), "-o", os.path.join(OBJ, host + ".o")])
@@ -67,7 +68,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             fh.write("\n".join(l for l in lg.splitlines() if "remark" in l) + "\n")
     summarize_resources(os.path.join(OBJ, "resource_usage.txt"), os.path.join(OBJ, "resource_summary.txt"))
     objs = [os.path.join(OBJ, f"jk_class_{n}.o") for n in range(NCLASS)]
-    objs += [os.path.join(OBJ, "jk_kernels.o"), os.path.join(OBJ, "jk_gemm.o")]
+    objs += [os.path.join(OBJ, src + "_dev.o") for src in DEVICE_SOURCES]
     objs += [os.path.join(OBJ, host + ".o") for host in HOST_SOURCES]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "jk.h"
+#include "jk_cd.h"
 #include "jk_internal.h"
 #include "jk_launch.h"
 
@@ -261,6 +262,32 @@ struct jk_basis_s {
         (void)hipSetDevice(cur);
     }
 };
+
+namespace jk {
+int basis_view(jk_basis_t h, BasisView* v) {
+    if (!h || !v) return fail(JK_EINVAL, "basis_view: NULL argument");
+    v->device = h->device;
+    v->ns = h->ns;
+    v->nf = h->nf;
+    v->spherical = h->spherical;
+    v->pairs = h->pairs;
+    for (int X = 0; X < kNumPairClass; ++X) v->pairs_of_class[X] = h->pairs_of_class[X];
+    v->uf0.assign(h->ns, 0);
+    v->nuf.assign(h->ns, 0);
+    for (int s = 0; s < h->ns; ++s) {
+        const int su = h->user_of_int[s];
+        v->uf0[s] = h->user_f0[su];
+        v->nuf[s] = h->user_f0[su + 1] - h->user_f0[su];
+    }
+    v->d_pairs = h->d_pairs;
+    v->d_prims = h->d_prims;
+    v->d_boys = h->d_boys;
+    v->d_boys32 = h->d_boys32;
+    v->d_umap = h->d_umap;
+    v->pslots = h->pslots;
+    return JK_OK;
+}
+}  // namespace jk
 
 namespace {
 

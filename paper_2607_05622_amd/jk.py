@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "jk.h")
 
 JK_OK, JK_EINVAL, JK_ENOMEM, JK_EDEVICE, JK_EUNSUPPORTED = 0, -1, -2, -3, -4
 JK_FP64, JK_MIXED = 0, 1
+JK_CD_MAX_VECTORS = 65535
 
 
 class JKError(RuntimeError):
@@ -122,6 +123,10 @@ def load(path: str = LIB_PATH):
     lib.jk_laplace_step.argtypes = [vp, i32, dp, dp, dp, i32, i32, dp, dp, i32, hd, dp, dp,
                                     ctypes.POINTER(jk_build_opts)]
     lib.jk_laplace_step.restype = c_int
+    lib.jk_cd_factor.argtypes = [vp, f64, f64, i32, dp, dp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.jk_cd_factor.restype = c_int
+    lib.jk_cd_jk.argtypes = [i32, i32, dp, i32, i32, dp, dp, dp, dp, vp]
+    lib.jk_cd_jk.restype = c_int
     _lib = lib
     return lib
 
@@ -470,3 +475,40 @@ def jk_laplace_step(h, D, C, eps, nocc: int, tau, opts: jk_build_opts | None = N
                                   _dev_mat(Rov, (nd, nocc, nvir), "Rov"), _dev_mat(Dn, (nd, len(tau), n, n), "Dnext"),
                                   ctypes.byref(o)))
     return J, K, Rov, Dn
+
+
+def jk_cd_factor(h, delta: float, screen_tol: float | None = None, max_vectors: int | None = None,
+                 device=None, stream=None):
+    """The factor of Eq. (cdfact): returns (B [nvec, n, n], pivots [nvec]) as
+    torch cuda tensors.  screen_tol defaults to 0.01 delta; max_vectors to
+    min(8 n, n (n + 1) / 2) (the call fails if more are needed)."""
+    import torch
+    n = jk_nbf(h)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if screen_tol is None:
+        screen_tol = 0.01 * delta
+    if max_vectors is None:
+        max_vectors = min(8 * n, n * (n + 1) // 2, JK_CD_MAX_VECTORS)
+    B = torch.empty((max(max_vectors, 1), n, n), dtype=torch.float64, device=dev)
+    piv = torch.empty((max(max_vectors, 1),), dtype=torch.int32, device=dev)
+    nvec = ctypes.c_int32(0)
+    _check(load().jk_cd_factor(h, float(delta), float(screen_tol), int(max_vectors), B.data_ptr(), piv.data_ptr(),
+                               ctypes.byref(nvec), _stream(stream, dev)))
+    k = nvec.value
+    return B[:k], piv[:k]
+
+
+def jk_cd_jk(B, U, V, want_j: bool = True, want_k: bool = True, stream=None):
+    """J and K of D[x] = U[x] V[x]^T (U, V [nd, n, r]) from the factor B
+    [nvec, n, n]: Eqs. (cdj) and (cdknonsym)."""
+    import torch
+    nvec, n = B.shape[0], U.shape[1]
+    nd, r = U.shape[0], U.shape[2]
+    J = torch.empty((nd, n, n), dtype=torch.float64, device=U.device) if want_j else None
+    K = torch.empty((nd, n, n), dtype=torch.float64, device=U.device) if want_k else None
+    if nvec == 0:
+        B = torch.empty((1, n, n), dtype=torch.float64, device=U.device)
+    _check(load().jk_cd_jk(n, nvec, _dev_mat(B, (max(nvec, 1), n, n), "B"), nd, r, _dev_mat(U, (nd, n, r), "U"),
+                           _dev_mat(V, (nd, n, r), "V"), J.data_ptr() if want_j else None,
+                           K.data_ptr() if want_k else None, _stream(stream, U.device)))
+    return J, K

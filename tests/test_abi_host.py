@@ -127,3 +127,15 @@ def test_tune_table_and_cache(tmp_path, lib):
     finally:
         for c, t in enumerate(old):
             jk.jk_tune_set(c, **t)
+
+
+def test_cd_entry_points_reject_bad_arguments_on_the_host():
+    """Argument checks of the CD entry points run before any device work."""
+    lib = jk.load()
+    n = ctypes.c_int32(0)
+    assert lib.jk_cd_factor(None, 1e-4, 1e-6, 10, None, None, ctypes.byref(n), None) == jk.JK_EINVAL
+    assert lib.jk_cd_jk(0, 1, None, 1, 1, None, None, None, None, None) == jk.JK_EINVAL
+    assert lib.jk_cd_jk(4, 1, None, 1, 0, None, None, None, None, None) == jk.JK_EINVAL
+    # neither J nor K wanted
+    assert lib.jk_cd_jk(4, 1, None, 1, 1, None, None, None, None, None) == jk.JK_EINVAL
+    assert "both NULL" in jk.jk_last_error()

@@ -1,0 +1,162 @@
+"""GPU parity of the Cholesky-factor (CD) J/K (Eqs. (cdfact)-(cdknonsym))
+through the C-ABI, against the CPU oracle (oracle/cd.py).
+
+* The factor: the same pivots (integers, chosen in FP64 on both sides with
+  the same tie rule), the same vectors and the same reconstruction B^T B.
+  A vector is a residual column, whose absolute rounding error is a few
+  ulps of the operator's largest entry (O(1)) per earlier vector, divided
+  by sqrt(d_p) >= sqrt(delta): the vectors are compared at 1e-12 /
+  sqrt(delta) absolute (1e-10 at delta = 1e-4), the reconstruction at
+  1e-12 of the operator's largest entry.
+* J and K from a factor: FP64 products, at 1e-12 of the largest element, on
+  seeded factors and densities of ragged sizes and of the benchmark's size.
+* End to end at the benchmark's size, where the oracle's operator does not
+  fit: the residual bound of a complete factor, |J_cd - J| <= delta sum|D|
+  entrywise, against the direct build."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cd
+from paper_2607_05622_amd import jk, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+CASES = [
+    # (seed, atoms, heavy, spherical, nprims, delta)
+    (601, 3, 2, 1, (3,), 1e-4),
+    (601, 3, 2, 1, (3,), 1e-8),
+    (602, 3, 2, 0, (3,), 1e-5),
+    (603, 3, 1, 1, (1, 2, 7, 16), 1e-6),
+    (604, 6, 4, 1, (3,), 1e-5),
+]
+
+
+@pytest.mark.parametrize("seed,atoms,heavy,spherical,nprims,delta", CASES)
+def test_factor_matches_oracle(dev, seed, atoms, heavy, spherical, nprims, delta):
+    b = synth.random_basis(seed, atoms, heavy, spherical=spherical, nprims=nprims)
+    n = b.nbf()
+    print(f"[cd factor] seed {seed}: {n} functions, delta {delta:g}", flush=True)
+    Bo, po = cd.pivoted_cholesky(cd.cd_matrix(b, 0.01 * delta), delta)
+    h = jk.jk_create_basis(b)
+    try:
+        # room for every pair: tight thresholds approach the operator's full rank
+        B, piv = jk.jk_cd_factor(h, delta, 0.01 * delta, max_vectors=n * (n + 1) // 2)
+        B, piv = B.cpu().numpy(), piv.cpu().numpy()
+    finally:
+        jk.jk_destroy(h)
+    assert B.shape[0] == Bo.shape[0] > 0
+    assert np.array_equal(piv.astype(np.int64), po)
+    Bu = cd.unpack(Bo, n)
+    assert np.abs(B - Bu).max() <= 1e-12 / np.sqrt(delta)
+    assert np.array_equal(B, B.transpose(0, 2, 1))
+    m, k = cd.pair_index(n)
+    Bp = B[:, m, k]
+    R, Ro = Bp.T @ Bp, Bo.T @ Bo
+    assert np.abs(R - Ro).max() <= 1e-12 * np.abs(Ro).max()
+
+
+def test_factor_edge_cases(dev):
+    b = synth.random_basis(605, 2, 1)
+    h = jk.jk_create_basis(b)
+    try:
+        # a threshold above every diagonal: the empty factor
+        B, piv = jk.jk_cd_factor(h, 1e6)
+        assert B.shape[0] == 0 and piv.shape[0] == 0
+        # a screen that keeps no quartet: nothing significant, the empty factor
+        B, _ = jk.jk_cd_factor(h, 1e-4, 1e12)
+        assert B.shape[0] == 0
+        # too few vectors allowed: an error, not a truncated factor
+        with pytest.raises(jk.JKError) as e:
+            jk.jk_cd_factor(h, 1e-8, max_vectors=3)
+        assert e.value.code == jk.JK_ENOMEM
+        # bad arguments
+        for args in [(0.0,), (-1.0,), (float("nan"),)]:
+            with pytest.raises(jk.JKError):
+                jk.jk_cd_factor(h, *args)
+        with pytest.raises(jk.JKError):
+            jk.jk_cd_factor(h, 1e-4, -1.0)
+        # exactly the vectors needed is enough
+        Bo, _ = cd.pivoted_cholesky(cd.cd_matrix(b, 1e-6), 1e-4)
+        B, _ = jk.jk_cd_factor(h, 1e-4, 1e-6, max_vectors=Bo.shape[0])
+        assert B.shape[0] == Bo.shape[0]
+    finally:
+        jk.jk_destroy(h)
+
+
+@pytest.mark.parametrize("n,nvec,nd,r", [(70, 37, 3, 5), (33, 1, 1, 1), (129, 300, 2, 65), (64, 2049, 1, 3)])
+def test_cd_jk_matches_oracle(dev, n, nvec, nd, r):
+    Bf = synth.random_symmetric_stack(n + nvec, nvec, n)
+    U, V = synth.random_factors(7 * n + r, nd, n, r)
+    J, K = jk.jk_cd_jk(_t(Bf, dev), _t(U, dev), _t(V, dev))
+    Jo, Ko = cd.cd_jk(Bf, U, V)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    for x in range(nd):
+        assert _relmax(J[x], Jo[x]) <= 1e-12, x
+        assert _relmax(K[x], Ko[x]) <= 1e-12, x
+    # one output alone, and the symmetric case U = V of Eq. (cdk)
+    _, K2 = jk.jk_cd_jk(_t(Bf, dev), _t(U, dev), _t(U, dev), want_j=False)
+    _, Ko2 = cd.cd_jk(Bf, U, U)
+    assert _relmax(K2.cpu().numpy(), Ko2) <= 1e-12
+
+
+def test_cd_jk_at_benchmark_size(dev):
+    """The contraction at the benchmark's shape (312 functions, 1800
+    vectors, rank 40), two densities checked in full."""
+    n, nvec, nd, r = 312, 1800, 2, 40
+    Bf = synth.random_symmetric_stack(11, nvec, n)
+    U, V = synth.random_factors(12, nd, n, r)
+    J, K = jk.jk_cd_jk(_t(Bf, dev), _t(U, dev), _t(V, dev))
+    Jo, Ko = cd.cd_jk(Bf, U, V)
+    assert _relmax(J.cpu().numpy(), Jo) <= 1e-12
+    assert _relmax(K.cpu().numpy(), Ko) <= 1e-12
+
+
+def test_cd_end_to_end_against_direct_build(dev):
+    """A complete factor at delta leaves a residual of at most delta per
+    entry, so |J_cd - J|, |K_cd - K| <= delta sum|D| entrywise; checked on the
+    312-function workload against the direct build (exact to ~1e-10)."""
+    import torch
+    w = synth.config1()
+    b = w.basis
+    n = b.nbf()
+    delta = 1e-4
+    U, V = synth.random_factors(13, 3, n, 40, scale=0.1)
+    h = jk.jk_create_basis(b)
+    try:
+        B, _ = jk.jk_cd_factor(h, delta)
+        print(f"[cd end-to-end] {n} functions: {B.shape[0]} vectors at delta {delta:g}", flush=True)
+        Ut, Vt = _t(U, dev), _t(V, dev)
+        J, K = jk.jk_cd_jk(B, Ut, Vt)
+        D = torch.bmm(Ut, Vt.transpose(1, 2).contiguous()).contiguous()
+        Jd, Kd = jk.jk_build(h, D)
+        torch.cuda.synchronize()
+    finally:
+        jk.jk_destroy(h)
+    bound = delta * np.abs(D.cpu().numpy()).sum(axis=(1, 2))
+    for x in range(3):
+        eJ = float((J[x] - Jd[x]).abs().max())
+        eK = float((K[x] - Kd[x]).abs().max())
+        assert eJ <= bound[x] + 1e-9 and eK <= bound[x] + 1e-9, (x, eJ, eK, bound[x])
+        # and far tighter in practice: relative Frobenius error
+        rj = float((J[x] - Jd[x]).norm() / Jd[x].norm())
+        rk = float((K[x] - Kd[x]).norm() / Kd[x].norm())
+        print(f"[cd end-to-end] density {x}: |dJ|/|J| = {rj:.2e}, |dK|/|K| = {rk:.2e}", flush=True)
+        assert rj < 1e-2 and rk < 1e-2
