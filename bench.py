@@ -51,8 +51,8 @@ def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        # the J/K build's sources (the Laplace-cascade files do not change it)
-        if name.endswith((".h", ".hip", ".cpp", ".py")) and not name.startswith(("jk_gemm", "jk_laplace", "jk_remez")):
+        # the J/K build's sources (the Laplace-cascade and CD files do not change it)
+        if name.endswith((".h", ".hip", ".cpp", ".py")) and not name.startswith(("jk_gemm", "jk_laplace", "jk_remez", "jk_cd")):
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -386,6 +386,7 @@ def main():
                     help="oracle sample stride on one core (0: 1024 for the large workload, 128 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-cascade edge measurement")
+    ap.add_argument("--no-cd", action="store_true", help="skip the Cholesky-factor J/K measurement")
     ap.add_argument("--serialized", action="store_true",
                     help="time only the profiled builds (launches one after another), for kernel-trace runs whose "
                          "per-kernel averages must match the roofline entry")
@@ -431,6 +432,8 @@ def main():
                             if k in med}
     if not args.no_laplace:
         result["laplace_edge"] = laplace_edge_bench(w, dev, stream, max(2, args.steps // 5))
+    if not args.no_cd:
+        result["cd"] = cd_bench(dev, stream, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on strided samples")
         st = args.cpu_stride or (64 if args.workload == "large" else 8)
@@ -490,6 +493,73 @@ def laplace_edge_bench(w, dev, stream, steps):
             "grid_max_error": gerr, "ms_per_edge": edge_ms, "edges_per_s": 1e3 / edge_ms,
             "dense_ms_per_edge": dense_ms, "dense_flops_per_edge": fock + dens, "dense_tflops": tf,
             "dense_frac_fp64_mfma_peak": tf / 78.6, "steps": steps}
+
+
+CD_DELTA = 1e-4
+
+
+def cd_bench(dev, stream, steps):
+    """The Cholesky-factor J/K (Eqs. (cdfact)-(cdknonsym)) on the 312-AO
+    workload's basis, against the direct build of the same densities: 40
+    seeded transition-like densities D = U V^T of rank 40 (the workload's
+    occupied count).  The factor is made once (delta = 1e-4, screen
+    0.01 delta); J and K from it, and the direct build, are timed with HIP
+    events on the stream.  The contraction's roofline is the whole call's
+    algorithmic flops (6 nd nvec n^2 r for K, 2 nd n^2 (r + 2 nvec) for J)
+    over its time: products on the FP64 matrix cores."""
+    import time
+
+    import torch
+
+    from paper_2607_05622_amd import jk, synth
+    w = workload("medium")
+    n = w.basis.nbf()
+    nd, r = 40, 40
+    U, V = synth.random_factors(31, nd, n, r, scale=0.1)
+    Ut = torch.tensor(U, dtype=torch.float64, device=dev)
+    Vt = torch.tensor(V, dtype=torch.float64, device=dev)
+    D = torch.bmm(Ut, Vt.transpose(1, 2).contiguous()).contiguous()
+    b = jk.JKBasis(w.basis)
+    try:
+        jk.jk_cd_factor(b.h, CD_DELTA, stream=stream)      # first call: allocator warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B, _ = jk.jk_cd_factor(b.h, CD_DELTA, stream=stream)
+        torch.cuda.synchronize()
+        factor_ms = 1e3 * (time.perf_counter() - t0)
+        nvec = B.shape[0]
+        J, K = jk.jk_cd_jk(B, Ut, Vt, stream=stream)
+        Jd, Kd = b.build(D, stream=stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            jk.jk_cd_jk(B, Ut, Vt, stream=stream)
+        ev[1].record(stream)
+        for _ in range(steps):
+            b.build(D, stream=stream)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        cd_ms = ev[0].elapsed_time(ev[1]) / steps
+        direct_ms = ev[1].elapsed_time(ev[2]) / steps
+        rj = max(float((J[x] - Jd[x]).norm() / Jd[x].norm()) for x in range(nd))
+        rk = max(float((K[x] - Kd[x]).norm() / Kd[x].norm()) for x in range(nd))
+    finally:
+        b.close()
+    flops = 6.0 * nd * nvec * n * n * r + 2.0 * nd * n * n * (r + 2 * nvec)
+    tf = flops / (cd_ms * 1e-3) / 1e12
+    log(f"cd: {nvec} vectors in {factor_ms:.0f} ms; J/K of {nd} densities {cd_ms:.1f} ms ({tf:.1f} TFLOP/s), "
+        f"direct {direct_ms:.1f} ms; rel err J {rj:.1e} K {rk:.1e}")
+    return {"what": f"Cholesky-factor J/K of {nd} rank-{r} densities D = U V^T on the medium-312ao basis, "
+                    f"against the direct build of the same densities",
+            "delta": CD_DELTA, "screen_tol": 0.01 * CD_DELTA, "nvec": nvec, "factor_ms": factor_ms,
+            "ms_per_build": cd_ms, "builds_per_s": 1e3 / cd_ms, "direct_ms_per_build": direct_ms,
+            "speedup_vs_direct": direct_ms / cd_ms,
+            "max_rel_frobenius_err_vs_direct": {"J": rj, "K": rk},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6,
+                         "traffic": None, "kernel": "jk_cd_jk (FP64 matrix-core products, whole call)",
+                         "flops_per_call": flops},
+            "steps": steps}
 
 
 def run_workload(args, name, steps, warmup, precision, dev, stream):

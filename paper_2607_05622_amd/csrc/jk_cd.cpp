@@ -93,6 +93,9 @@ const int kPairLs[kNumPairClass][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {
 
 // Tile elements per integral launch (256 MB of FP64 tiles).
 constexpr long long kCdTileElems = 32ll << 20;
+// Budget of one density group's half-transforms B U and B V in jk_cd_jk
+// (elements: 16 GB).
+constexpr long long kCdGroupElems = 2ll << 30;
 // Steps between two reads of the loop state at the start (doubling up to 256).
 constexpr int kCdPollFirst = 16, kCdPollMax = 256;
 
@@ -303,9 +306,14 @@ int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, c
     const int ng = static_cast<int>(nn / kg), nk = static_cast<int>(vr / kk);
     const long long gparts = static_cast<long long>(ng + 1) * nvec * nd;
     const long long kparts = static_cast<long long>(nk + 1) * nn;
-    // scratch: D [nd][nf][nf] (J), gamma parts and gamma (J), BU, BV [nf][nvec][r] and K parts (K)
+    // K runs over groups of xg densities whose half-transforms B U, B V fit
+    // the group budget together
+    const long long per = 2 * static_cast<long long>(nf) * vr;
+    const int xg = static_cast<int>(std::max<long long>(1, std::min<long long>(nd, kCdGroupElems / per)));
+    // scratch: D [nd][nf][nf], gamma parts and gamma (J); BU, BV [xg][nf][nvec r],
+    // the group's factors [nf][xg r] twice and the K parts (K)
     const long long wj = J ? nd * nn + gparts + static_cast<long long>(nvec) * nd : 0;
-    const long long wk = K ? 2 * nf * vr + kparts : 0;
+    const long long wk = K ? xg * per + 2 * static_cast<long long>(nf) * xg * r + kparts : 0;
     Scratch sc(s);
     if (sc.get(static_cast<size_t>(wj + wk) * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
@@ -343,34 +351,46 @@ int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, c
     }
     if (K) {
         double* BU = w + wj;
-        double* BV = BU + nf * vr;
-        double* kp = BV + nf * vr;
-        for (int x = 0; x < nd; ++x) {
-            const double* Ux = U + static_cast<long long>(x) * nf * r;
-            const double* Vx = V + static_cast<long long>(x) * nf * r;
-            // BU[mu][Q][m] = sum_k B[Q][mu][k] U[k][m], one product per Q
-            GemmArgs bu{B, Ux, BU, nf, r, nf, 0, 0, nf, r, static_cast<int>(vr), nn, 0, r, 1.0, 0.0};
+        double* BV = BU + xg * (per / 2);
+        double* UG = BV + xg * (per / 2);
+        double* VG = UG + static_cast<long long>(nf) * xg * r;
+        double* kp = VG + static_cast<long long>(nf) * xg * r;
+        for (int x0 = 0; x0 < nd; x0 += xg) {
+            const int nx = std::min(xg, nd - x0);
+            const int wcol = nx * r;
+            CDC(launch_cd_gather(U, nf, r, x0, nx, UG, s));
+            CDC(launch_cd_gather(V, nf, r, x0, nx, VG, s));
+            // BU_x[mu][(Q, m)] = sum_k B[Q][mu][k] U[x][k][m] for the whole group at
+            // once: one product per Q against the group's factors side by side,
+            // its column groups of r stored density-major
+            GemmArgs bu{B, UG, BU, nf, wcol, nf, 0, 0, nf, wcol, static_cast<int>(vr), nn, 0, r, 1.0, 0.0,
+                        r, static_cast<long long>(nf) * vr};
             CDC(launch_gemm(bu, nvec, s));
-            GemmArgs bv{B, Vx, BV, nf, r, nf, 0, 0, nf, r, static_cast<int>(vr), nn, 0, r, 1.0, 0.0};
+            GemmArgs bv{B, VG, BV, nf, wcol, nf, 0, 0, nf, wcol, static_cast<int>(vr), nn, 0, r, 1.0, 0.0,
+                        r, static_cast<long long>(nf) * vr};
             CDC(launch_gemm(bv, nvec, s));
-            // K[mu][nu] = sum_(Q,m) BU[mu][(Q,m)] BV[nu][(Q,m)], split over (Q, m)
-            double* Kx = K + static_cast<long long>(x) * nn;
-            int nb = 0;
-            if (nk > 0) {
-                GemmArgs a{BU, BV, kp, nf, nf, static_cast<int>(kk), 0, 1, static_cast<int>(vr), static_cast<int>(vr),
-                           nf, kk, kk, nn, 1.0, 0.0};
-                CDC(launch_gemm(a, nk, s));
-                nb = nk;
+            for (int xl = 0; xl < nx; ++xl) {
+                const double* BUx = BU + static_cast<long long>(xl) * nf * vr;
+                const double* BVx = BV + static_cast<long long>(xl) * nf * vr;
+                // K[mu][nu] = sum_(Q,m) BU_x[mu][(Q,m)] BV_x[nu][(Q,m)], split over (Q, m)
+                double* Kx = K + static_cast<long long>(x0 + xl) * nn;
+                int nb = 0;
+                if (nk > 0) {
+                    GemmArgs a{BUx, BVx, kp, nf, nf, static_cast<int>(kk), 0, 1, static_cast<int>(vr),
+                               static_cast<int>(vr), nf, kk, kk, nn, 1.0, 0.0};
+                    CDC(launch_gemm(a, nk, s));
+                    nb = nk;
+                }
+                const long long rem = vr - static_cast<long long>(nk) * kk;
+                if (rem > 0) {
+                    GemmArgs a{BUx + nk * kk, BVx + nk * kk, kp + static_cast<long long>(nb) * nn, nf, nf,
+                               static_cast<int>(rem), 0, 1, static_cast<int>(vr), static_cast<int>(vr), nf, 0, 0, 0,
+                               1.0, 0.0};
+                    CDC(launch_gemm(a, 1, s));
+                    ++nb;
+                }
+                CDC(launch_cd_sum(kp, nb, nn, nn, Kx, s));
             }
-            const long long rem = vr - static_cast<long long>(nk) * kk;
-            if (rem > 0) {
-                GemmArgs a{BU + nk * kk, BV + nk * kk, kp + static_cast<long long>(nb) * nn, nf, nf,
-                           static_cast<int>(rem), 0, 1, static_cast<int>(vr), static_cast<int>(vr), nf, 0, 0, 0, 1.0,
-                           0.0};
-                CDC(launch_gemm(a, 1, s));
-                ++nb;
-            }
-            CDC(launch_cd_sum(kp, nb, nn, nn, Kx, s));
         }
     }
     return JK_OK;

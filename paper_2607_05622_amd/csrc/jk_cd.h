@@ -67,6 +67,8 @@ hipError_t launch_cd_step(const double* V, long long n, double* Bc, double* d, i
 hipError_t launch_cd_expand(const double* Bc, long long nsig, int nvec, const int* pm, const int* pn, int nf,
                             double* B, const int* piv, const long long* sig_pair, int* pivots_out,
                             hipStream_t s);
+// out[k][xl r + m] = in[x0 + xl][k][m] (in: [nd][nf][r]), xl < xg
+hipError_t launch_cd_gather(const double* in, int nf, int r, int x0, int xg, double* out, hipStream_t s);
 // out[i] = sum over b < nb of parts[b * stride + i], i < n
 hipError_t launch_cd_sum(const double* parts, int nb, long long stride, long long n, double* out, hipStream_t s);
 

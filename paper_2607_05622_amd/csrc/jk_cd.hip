@@ -163,6 +163,17 @@ __global__ void k_cd_sum(const double* __restrict__ parts, int nb, long long str
     out[i] = s;
 }
 
+// out[k][xl r + m] = in[x0 + xl][k][m] for xl < xg: the density group's
+// factors side by side, as one nf x (xg r) operand
+__global__ void k_cd_gather(const double* __restrict__ in, int nf, int r, int x0, int xg, double* __restrict__ out) {
+    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const long long w = static_cast<long long>(xg) * r;
+    if (t >= w * nf) return;
+    const long long k = t / w, c = t - k * w;
+    const long long xl = c / r, m = c - xl * r;
+    out[t] = in[((x0 + xl) * nf + k) * r + m];
+}
+
 unsigned blocks_of(long long n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
 
 }  // namespace
@@ -193,6 +204,13 @@ hipError_t launch_cd_expand(const double* Bc, long long nsig, int nvec, const in
     if (nvec == 0) return hipSuccess;
     const dim3 grid(blocks_of(nsig > 0 ? nsig : 1, 256), nvec);
     hipLaunchKernelGGL(k_cd_expand, grid, dim3(256), 0, s, Bc, nsig, pm, pn, nf, B, piv, sig_pair, pivots_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cd_gather(const double* in, int nf, int r, int x0, int xg, double* out, hipStream_t s) {
+    const long long n = static_cast<long long>(nf) * xg * r;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cd_gather, dim3(blocks_of(n, 256)), dim3(256), 0, s, in, nf, r, x0, xg, out);
     return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@ namespace jk {
 // C[b] = alpha op(A[b]) op(B[b]) + beta C[b] for b < batch; row-major with
 // leading dimensions lda, ldb, ldc and batch strides sa, sb, sc (elements;
 // 0 repeats one matrix); op(A) is M x K (A[k][m] read when ta), op(B) K x N
-// (B[n][k] read when tb).
+// (B[n][k] read when tb).  With gcols > 0 the columns of C come in groups of
+// gcols, group g starting gstride elements after group g - 1 (column n of
+// row m at m ldc + (n / gcols) gstride + n % gcols).
 struct GemmArgs {
     const double* A;
     const double* B;
@@ -17,6 +19,8 @@ struct GemmArgs {
     int M, N, K, ta, tb, lda, ldb, ldc;
     long long sa, sb, sc;
     double alpha, beta;
+    int gcols;
+    long long gstride;
 };
 hipError_t launch_gemm(const GemmArgs& g, int batch, hipStream_t s);
 

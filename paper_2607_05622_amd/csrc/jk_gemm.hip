@@ -16,8 +16,47 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // waves computes a 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2
 // tiles of v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] and holds C[4 r + l / 16][l % 16] in element r), over K
-// in chunks of 16 staged in LDS as [k][m] and [k][n].
-constexpr int kTile = 64, kChunk = 16;
+// in chunks of 16 staged in LDS as [k][m] and [k][n].  The next chunk's
+// global loads are issued into registers before the current chunk's
+// products, so their latency overlaps the matrix-core work.
+constexpr int kTile = 64, kChunk = 16, kPer = kTile * kChunk / 256;
+
+struct ChunkRegs {
+    double a[kPer], b[kPer];
+};
+
+__device__ inline void load_chunk(const GemmArgs& g, const double* __restrict__ A, const double* __restrict__ B,
+                                  int m0, int n0, int k0, int tid, ChunkRegs& r) {
+    // the element order follows the memory order so loads coalesce
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + 256 * u;
+        int mm, kk;
+        if (g.ta) {   // op(A)[m][k] = A[k][m]
+            kk = e / kTile;
+            mm = e - kk * kTile;
+        } else {
+            mm = e / kChunk;
+            kk = e - mm * kChunk;
+        }
+        const int gm = m0 + mm, gk = k0 + kk;
+        r.a[u] = (gm < g.M && gk < g.K)
+                     ? (g.ta ? A[static_cast<long long>(gk) * g.lda + gm] : A[static_cast<long long>(gm) * g.lda + gk])
+                     : 0.0;
+        int nn;
+        if (g.tb) {   // op(B)[k][n] = B[n][k]
+            nn = e / kChunk;
+            kk = e - nn * kChunk;
+        } else {
+            kk = e / kTile;
+            nn = e - kk * kTile;
+        }
+        const int gn = n0 + nn, gk2 = k0 + kk;
+        r.b[u] = (gn < g.N && gk2 < g.K)
+                     ? (g.tb ? B[static_cast<long long>(gn) * g.ldb + gk2] : B[static_cast<long long>(gk2) * g.ldb + gn])
+                     : 0.0;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ double sA[kChunk][kTile + 1];
@@ -35,37 +74,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    ChunkRegs r;
+    load_chunk(g, A, B, m0, n0, 0, tid, r);
     for (int k0 = 0; k0 < g.K; k0 += kChunk) {
-        // op(A) chunk: 64 rows x 16 k; op(B) chunk: 16 k x 64 columns.  The
-        // element order follows the memory order so loads coalesce.
 #pragma unroll
-        for (int e = tid; e < kTile * kChunk; e += 256) {
-            int mm, kk;
-            if (g.ta) {   // op(A)[m][k] = A[k][m]
-                kk = e / kTile;
-                mm = e - kk * kTile;
-            } else {
-                mm = e / kChunk;
-                kk = e - mm * kChunk;
-            }
-            const int gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < g.M && gk < g.K) v = g.ta ? A[static_cast<long long>(gk) * g.lda + gm] : A[static_cast<long long>(gm) * g.lda + gk];
-            sA[kk][mm] = v;
-            int nn;
-            if (g.tb) {   // op(B)[k][n] = B[n][k]
-                nn = e / kChunk;
-                kk = e - nn * kChunk;
-            } else {
-                kk = e / kTile;
-                nn = e - kk * kTile;
-            }
-            const int gn = n0 + nn, gk2 = k0 + kk;
-            double u = 0.0;
-            if (gn < g.N && gk2 < g.K) u = g.tb ? B[static_cast<long long>(gn) * g.ldb + gk2] : B[static_cast<long long>(gk2) * g.ldb + gn];
-            sB[kk][nn] = u;
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            if (g.ta) sA[e / kTile][e % kTile] = r.a[u];
+            else sA[e % kChunk][e / kChunk] = r.a[u];
+            if (g.tb) sB[e % kChunk][e / kChunk] = r.b[u];
+            else sB[e / kTile][e % kTile] = r.b[u];
         }
         __syncthreads();
+        if (k0 + kChunk < g.K) load_chunk(g, A, B, m0, n0, k0 + kChunk, tid, r);
 #pragma unroll
         for (int ks = 0; ks < kChunk; ks += 4) {
             double a[2], bb[2];
@@ -85,11 +106,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * i + 4 * r + r4, gn = n0 + wn + 16 * j + c16;
+            for (int rr = 0; rr < 4; ++rr) {
+                const int gm = m0 + wm + 16 * i + 4 * rr + r4, gn = n0 + wn + 16 * j + c16;
                 if (gm < g.M && gn < g.N) {
-                    double* const p = C + static_cast<long long>(gm) * g.ldc + gn;
-                    *p = g.beta == 0.0 ? g.alpha * acc[i][j][r] : fma(g.alpha, acc[i][j][r], g.beta * *p);
+                    const long long col = g.gcols > 0 ? (gn / g.gcols) * g.gstride + gn % g.gcols : gn;
+                    double* const p = C + static_cast<long long>(gm) * g.ldc + col;
+                    *p = g.beta == 0.0 ? g.alpha * acc[i][j][rr] : fma(g.alpha, acc[i][j][rr], g.beta * *p);
                 }
             }
 }
