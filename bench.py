@@ -387,6 +387,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-cascade edge measurement")
     ap.add_argument("--no-cd", action="store_true", help="skip the Cholesky-factor J/K measurement")
+    ap.add_argument("--cd-only", action="store_true",
+                    help="only the Cholesky-factor J/K measurement (for kernel-trace runs of its kernels)")
     ap.add_argument("--serialized", action="store_true",
                     help="time only the profiled builds (launches one after another), for kernel-trace runs whose "
                          "per-kernel averages must match the roofline entry")
@@ -423,6 +425,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.cd_only:
+        print(json.dumps({"cd": cd_bench(dev, stream, max(3, args.steps // 2))}), flush=True)
+        return
     result, w, outs = run_workload(args, args.workload, args.steps, args.warmup, args.precision, dev, stream)
     if args.workload == "large" and not args.no_medium:
         med, _, _ = run_workload(args, "medium", 2 * args.steps, args.warmup, args.precision, dev, stream)
