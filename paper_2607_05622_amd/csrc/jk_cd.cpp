@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <thread>
 #include <vector>
 
 #include "jk.h"
@@ -151,19 +152,40 @@ int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vect
     if (nsig == 0) return JK_OK;   // nothing significant: the factor is empty
 
     // kept quartets per class (canonical: bra pair class >= ket pair class,
-    // ket <= bra within one class), Q_ab Q_cd >= screen_tol
+    // ket <= bra within one class), Q_ab Q_cd >= screen_tol: per bra pair
+    // the kets in descending Q up to the first that fails, bra pairs spread
+    // over host threads (the order of a class's quartets does not matter:
+    // every operator entry has one writer)
+    std::vector<int> ksorted[kNumPairClass];
+    for (int Y = 0; Y < kNumPairClass; ++Y) {
+        ksorted[Y] = v.pairs_of_class[Y];
+        std::sort(ksorted[Y].begin(), ksorted[Y].end(),
+                  [&](int a, int b) { return v.pairs[a].q > v.pairs[b].q; });
+    }
+    const int nthr = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
     std::vector<int2> qs[kNumClass];
     long long maxq = 0;
     for (int X = 0; X < kNumPairClass; ++X)
         for (int Y = 0; Y <= X; ++Y) {
+            const std::vector<int>& bra = v.pairs_of_class[X];
+            const std::vector<int>& ket = ksorted[Y];
+            std::vector<std::vector<int2>> part(nthr);
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nthr; ++t)
+                pool.emplace_back([&, t]() {
+                    for (size_t i = t; i < bra.size(); i += nthr) {
+                        const int b = bra[i];
+                        const double qb = v.pairs[b].q;
+                        for (int k : ket) {
+                            if (qb * v.pairs[k].q < screen_tol) break;
+                            if (X == Y && k > b) continue;
+                            part[t].push_back(make_int2(b, k));
+                        }
+                    }
+                });
+            for (auto& th : pool) th.join();
             std::vector<int2>& out = qs[quartet_class(X, Y)];
-            for (int b : v.pairs_of_class[X]) {
-                const double qb = v.pairs[b].q;
-                for (int k : v.pairs_of_class[Y]) {
-                    if (X == Y && k > b) continue;
-                    if (qb * v.pairs[k].q >= screen_tol) out.push_back(make_int2(b, k));
-                }
-            }
+            for (auto& pv : part) out.insert(out.end(), pv.begin(), pv.end());
             maxq = std::max<long long>(maxq, static_cast<long long>(out.size()));
         }
 
