@@ -324,10 +324,10 @@ int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, c
     }
     const long long vr = static_cast<long long>(nvec) * r;
     // split-K chunks of the two long contractions (gamma over nf^2, K over nvec r)
-    const long long kg = 4096, kk = 2048;
-    const int ng = static_cast<int>(nn / kg), nk = static_cast<int>(vr / kk);
-    const long long gparts = static_cast<long long>(ng + 1) * nvec * nd;
-    const long long kparts = static_cast<long long>(nk + 1) * nn;
+    const long long kg = 4096, kk = 1024;
+    const int ng = static_cast<int>((nn + kg - 1) / kg), nk = static_cast<int>((vr + kk - 1) / kk);
+    const long long gparts = static_cast<long long>(ng) * nvec * nd;
+    const long long kparts = static_cast<long long>(nk) * nn;
     // K runs over groups of xg densities whose half-transforms B U, B V fit
     // the group budget together
     const long long per = 2 * static_cast<long long>(nf) * vr;
@@ -350,22 +350,13 @@ int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, c
         GemmArgs g{U, V, D, nf, nf, r, 0, 1, r, r, nf, static_cast<long long>(nf) * r,
                    static_cast<long long>(nf) * r, nn, 1.0, 0.0};
         CDC(launch_gemm(g, nd, s));
-        // gamma[Q][x] = sum_P B[Q][P] D[x][P]: split over P in chunks of kg, then summed
-        int nb = 0;
-        if (ng > 0) {
-            GemmArgs a{B, D, gp, nvec, nd, static_cast<int>(kg), 0, 1, static_cast<int>(nn), static_cast<int>(nn), nd,
-                       kg, kg, static_cast<long long>(nvec) * nd, 1.0, 0.0};
-            CDC(launch_gemm(a, ng, s));
-            nb = ng;
-        }
-        const long long rem = nn - static_cast<long long>(ng) * kg;
-        if (rem > 0) {
-            GemmArgs a{B + ng * kg, D + ng * kg, gp + static_cast<long long>(nb) * nvec * nd, nvec, nd,
-                       static_cast<int>(rem), 0, 1, static_cast<int>(nn), static_cast<int>(nn), nd, 0, 0, 0, 1.0, 0.0};
-            CDC(launch_gemm(a, 1, s));
-            ++nb;
-        }
-        CDC(launch_cd_sum(gp, nb, static_cast<long long>(nvec) * nd, static_cast<long long>(nvec) * nd, gamma, s));
+        // gamma[Q][x] = sum_P B[Q][P] D[x][P]: split over P in ng chunks of kg
+        // (the last one shorter), then summed
+        GemmArgs a{B, D, gp, nvec, nd, static_cast<int>(kg), 0, 1, static_cast<int>(nn), static_cast<int>(nn), nd,
+                   kg, kg, static_cast<long long>(nvec) * nd, 1.0, 0.0};
+        a.klast = static_cast<int>(nn - (ng - 1) * kg);
+        CDC(launch_gemm(a, ng, s));
+        CDC(launch_cd_sum(gp, ng, static_cast<long long>(nvec) * nd, static_cast<long long>(nvec) * nd, gamma, s));
         // J[x][P] = sum_Q gamma[Q][x] B[Q][P]
         GemmArgs jj{gamma, B, J, nd, static_cast<int>(nn), nvec, 1, 0, nd, static_cast<int>(nn), static_cast<int>(nn),
                     0, 0, 0, 1.0, 0.0};
@@ -395,22 +386,13 @@ int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, c
                 const double* BUx = BU + static_cast<long long>(xl) * nf * vr;
                 const double* BVx = BV + static_cast<long long>(xl) * nf * vr;
                 // K[mu][nu] = sum_(Q,m) BU_x[mu][(Q,m)] BV_x[nu][(Q,m)], split over (Q, m)
+                // in nk chunks of kk (the last one shorter)
                 double* Kx = K + static_cast<long long>(x0 + xl) * nn;
-                int nb = 0;
-                if (nk > 0) {
-                    GemmArgs a{BUx, BVx, kp, nf, nf, static_cast<int>(kk), 0, 1, static_cast<int>(vr),
-                               static_cast<int>(vr), nf, kk, kk, nn, 1.0, 0.0};
-                    CDC(launch_gemm(a, nk, s));
-                    nb = nk;
-                }
-                const long long rem = vr - static_cast<long long>(nk) * kk;
-                if (rem > 0) {
-                    GemmArgs a{BUx + nk * kk, BVx + nk * kk, kp + static_cast<long long>(nb) * nn, nf, nf,
-                               static_cast<int>(rem), 0, 1, static_cast<int>(vr), static_cast<int>(vr), nf, 0, 0, 0,
-                               1.0, 0.0};
-                    CDC(launch_gemm(a, 1, s));
-                    ++nb;
-                }
+                GemmArgs a{BUx, BVx, kp, nf, nf, static_cast<int>(kk), 0, 1, static_cast<int>(vr),
+                           static_cast<int>(vr), nf, kk, kk, nn, 1.0, 0.0};
+                a.klast = static_cast<int>(vr - (nk - 1) * kk);
+                CDC(launch_gemm(a, nk, s));
+                const int nb = nk;
                 CDC(launch_cd_sum(kp, nb, nn, nn, Kx, s));
             }
         }

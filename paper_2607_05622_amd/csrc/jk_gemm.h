@@ -11,7 +11,9 @@ namespace jk {
 // 0 repeats one matrix); op(A) is M x K (A[k][m] read when ta), op(B) K x N
 // (B[n][k] read when tb).  With gcols > 0 the columns of C come in groups of
 // gcols, group g starting gstride elements after group g - 1 (column n of
-// row m at m ldc + (n / gcols) gstride + n % gcols).
+// row m at m ldc + (n / gcols) gstride + n % gcols).  With klast > 0 the
+// last batch sums over its first klast values of k only (a split-K
+// product whose last piece is shorter).
 struct GemmArgs {
     const double* A;
     const double* B;
@@ -21,6 +23,7 @@ struct GemmArgs {
     double alpha, beta;
     int gcols;
     long long gstride;
+    int klast;
 };
 hipError_t launch_gemm(const GemmArgs& g, int batch, hipStream_t s);
 

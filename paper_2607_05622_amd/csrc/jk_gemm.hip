@@ -26,7 +26,7 @@ struct ChunkRegs {
 };
 
 __device__ inline void load_chunk(const GemmArgs& g, const double* __restrict__ A, const double* __restrict__ B,
-                                  int m0, int n0, int k0, int tid, ChunkRegs& r) {
+                                  int m0, int n0, int k0, int K, int tid, ChunkRegs& r) {
     // the element order follows the memory order so loads coalesce
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -40,7 +40,7 @@ __device__ inline void load_chunk(const GemmArgs& g, const double* __restrict__ 
             kk = e - mm * kChunk;
         }
         const int gm = m0 + mm, gk = k0 + kk;
-        r.a[u] = (gm < g.M && gk < g.K)
+        r.a[u] = (gm < g.M && gk < K)
                      ? (g.ta ? A[static_cast<long long>(gk) * g.lda + gm] : A[static_cast<long long>(gm) * g.lda + gk])
                      : 0.0;
         int nn;
@@ -52,7 +52,7 @@ __device__ inline void load_chunk(const GemmArgs& g, const double* __restrict__ 
             nn = e - kk * kTile;
         }
         const int gn = n0 + nn, gk2 = k0 + kk;
-        r.b[u] = (gn < g.N && gk2 < g.K)
+        r.b[u] = (gn < g.N && gk2 < K)
                      ? (g.tb ? B[static_cast<long long>(gn) * g.ldb + gk2] : B[static_cast<long long>(gk2) * g.ldb + gn])
                      : 0.0;
     }
@@ -74,9 +74,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int K = g.klast > 0 && blockIdx.z == gridDim.z - 1 ? g.klast : g.K;
     ChunkRegs r;
-    load_chunk(g, A, B, m0, n0, 0, tid, r);
-    for (int k0 = 0; k0 < g.K; k0 += kChunk) {
+    load_chunk(g, A, B, m0, n0, 0, K, tid, r);
+    for (int k0 = 0; k0 < K; k0 += kChunk) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + 256 * u;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             else sB[e / kTile][e % kTile] = r.b[u];
         }
         __syncthreads();
-        if (k0 + kChunk < g.K) load_chunk(g, A, B, m0, n0, k0 + kChunk, tid, r);
+        if (k0 + kChunk < K) load_chunk(g, A, B, m0, n0, k0 + kChunk, K, tid, r);
 #pragma unroll
         for (int ks = 0; ks < kChunk; ks += 4) {
             double a[2], bb[2];
