@@ -389,6 +389,8 @@ def main():
     ap.add_argument("--no-cd", action="store_true", help="skip the Cholesky-factor J/K measurement")
     ap.add_argument("--cd-only", action="store_true",
                     help="only the Cholesky-factor J/K measurement (for kernel-trace runs of its kernels)")
+    ap.add_argument("--cd-workload", default="large", choices=["medium", "large"],
+                    help="workload of --cd-only")
     ap.add_argument("--serialized", action="store_true",
                     help="time only the profiled builds (launches one after another), for kernel-trace runs whose "
                          "per-kernel averages must match the roofline entry")
@@ -426,7 +428,7 @@ def main():
         del src, dst
 
     if args.cd_only:
-        print(json.dumps({"cd": cd_bench(dev, stream, max(3, args.steps // 2))}), flush=True)
+        print(json.dumps({"cd": cd_bench(dev, stream, max(3, args.steps // 2), args.cd_workload)}), flush=True)
         return
     result, w, outs = run_workload(args, args.workload, args.steps, args.warmup, args.precision, dev, stream)
     if args.workload == "large" and not args.no_medium:
@@ -438,7 +440,8 @@ def main():
     if not args.no_laplace:
         result["laplace_edge"] = laplace_edge_bench(w, dev, stream, max(2, args.steps // 5))
     if not args.no_cd:
-        result["cd"] = cd_bench(dev, stream, max(3, args.steps // 2))
+        result["cd"] = cd_bench(dev, stream, max(3, args.steps // 2), "large")
+        result["cd"]["medium"] = cd_bench(dev, stream, max(3, args.steps // 2), "medium")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on strided samples")
         st = args.cpu_stride or (64 if args.workload == "large" else 8)
@@ -503,11 +506,11 @@ def laplace_edge_bench(w, dev, stream, steps):
 CD_DELTA = 1e-4
 
 
-def cd_bench(dev, stream, steps):
-    """The Cholesky-factor J/K (Eqs. (cdfact)-(cdknonsym)) on the 312-AO
-    workload's basis, against the direct build of the same densities: 40
-    seeded transition-like densities D = U V^T of rank 40 (the workload's
-    occupied count).  The factor is made once (delta = 1e-4, screen
+def cd_bench(dev, stream, steps, name="large"):
+    """The Cholesky-factor J/K (Eqs. (cdfact)-(cdknonsym)) on a workload's
+    basis, against the direct build of the same densities: 40 seeded
+    transition-like densities D = U V^T of rank 40 (the workloads' occupied
+    count).  The factor is made once (delta = 1e-4, screen
     0.01 delta); J and K from it, and the direct build, are timed with HIP
     events on the stream.  The contraction's roofline is the whole call's
     algorithmic flops (6 nd nvec n^2 r for K, 2 nd n^2 (r + 2 nvec) for J)
@@ -517,7 +520,7 @@ def cd_bench(dev, stream, steps):
     import torch
 
     from paper_2607_05622_amd import jk, synth
-    w = workload("medium")
+    w = workload(name)
     n = w.basis.nbf()
     nd, r = 40, 40
     U, V = synth.random_factors(31, nd, n, r, scale=0.1)
@@ -553,9 +556,9 @@ def cd_bench(dev, stream, steps):
         b.close()
     flops = 6.0 * nd * nvec * n * n * r + 2.0 * nd * n * n * (r + 2 * nvec)
     tf = flops / (cd_ms * 1e-3) / 1e12
-    log(f"cd: {nvec} vectors in {factor_ms:.0f} ms; J/K of {nd} densities {cd_ms:.1f} ms ({tf:.1f} TFLOP/s), "
+    log(f"cd {w.name}: {nvec} vectors in {factor_ms:.0f} ms; J/K of {nd} densities {cd_ms:.1f} ms ({tf:.1f} TFLOP/s), "
         f"direct {direct_ms:.1f} ms; rel err J {rj:.1e} K {rk:.1e}")
-    return {"what": f"Cholesky-factor J/K of {nd} rank-{r} densities D = U V^T on the medium-312ao basis, "
+    return {"what": f"Cholesky-factor J/K of {nd} rank-{r} densities D = U V^T on the {w.name} basis, "
                     f"against the direct build of the same densities",
             "delta": CD_DELTA, "screen_tol": 0.01 * CD_DELTA, "nvec": nvec, "factor_ms": factor_ms,
             "ms_per_build": cd_ms, "builds_per_s": 1e3 / cd_ms, "direct_ms_per_build": direct_ms,

@@ -129,22 +129,18 @@ def test_cd_jk_at_benchmark_size(dev):
     assert _relmax(K.cpu().numpy(), Ko) <= 1e-12
 
 
-def test_cd_end_to_end_against_direct_build(dev):
-    """A complete factor at delta leaves a residual of at most delta per
-    entry, so |J_cd - J|, |K_cd - K| <= delta sum|D| entrywise; checked on the
-    312-function workload against the direct build (exact to ~1e-10)."""
+def _end_to_end(dev, w, delta, seed):
     import torch
-    w = synth.config1()
     b = w.basis
     n = b.nbf()
-    delta = 1e-4
-    U, V = synth.random_factors(13, 3, n, 40, scale=0.1)
+    U, V = synth.random_factors(seed, 3, n, 40, scale=0.1)
     h = jk.jk_create_basis(b)
     try:
         B, _ = jk.jk_cd_factor(h, delta)
         print(f"[cd end-to-end] {n} functions: {B.shape[0]} vectors at delta {delta:g}", flush=True)
         Ut, Vt = _t(U, dev), _t(V, dev)
         J, K = jk.jk_cd_jk(B, Ut, Vt)
+        del B
         D = torch.bmm(Ut, Vt.transpose(1, 2).contiguous()).contiguous()
         Jd, Kd = jk.jk_build(h, D)
         torch.cuda.synchronize()
@@ -160,3 +156,16 @@ def test_cd_end_to_end_against_direct_build(dev):
         rk = float((K[x] - Kd[x]).norm() / Kd[x].norm())
         print(f"[cd end-to-end] density {x}: |dJ|/|J| = {rj:.2e}, |dK|/|K| = {rk:.2e}", flush=True)
         assert rj < 1e-2 and rk < 1e-2
+
+
+def test_cd_end_to_end_against_direct_build(dev):
+    """A complete factor at delta leaves a residual of at most delta per
+    entry, so |J_cd - J|, |K_cd - K| <= delta sum|D| entrywise; checked on the
+    312-function workload against the direct build (exact to ~1e-10)."""
+    _end_to_end(dev, synth.config1(), 1e-4, 13)
+
+
+def test_cd_end_to_end_large_workload(dev):
+    """The same bound on the 620-function workload (105,802 significant
+    pairs: a 90 GB operator pool)."""
+    _end_to_end(dev, synth.config2(), 1e-4, 14)
