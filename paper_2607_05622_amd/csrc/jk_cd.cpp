@@ -198,7 +198,7 @@ int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vect
                      nsig, max_vectors, need / 1e9, free_b / 1e9);
 
     Buffers buf;
-    double *V = nullptr, *Bc = nullptr, *d = nullptr, *tiles = nullptr, *scr = nullptr;
+    double *V = nullptr, *Bc = nullptr, *d = nullptr, *bmax = nullptr, *tiles = nullptr, *scr = nullptr;
     int *dcidx = nullptr, *dpm = nullptr, *dpn = nullptr, *duf0 = nullptr, *piv = nullptr;
     long long* dsig = nullptr;
     int2* dq = nullptr;
@@ -207,6 +207,7 @@ int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vect
     CDC(buf.get(&V, static_cast<size_t>(nsig) * nsig));
     CDC(buf.get(&Bc, static_cast<size_t>(max_vectors) * nsig));
     CDC(buf.get(&d, nsig));
+    CDC(buf.get(&bmax, (nsig + 255) / 256));
     CDC(buf.get(&tiles, kCdTileElems));
     CDC(buf.get(&scr, kCdTileElems));
     CDC(buf.get(&dcidx, cidx.size()));
@@ -282,12 +283,12 @@ int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vect
 
     // pivoted Cholesky: device-side steps, the host reading the loop state
     // after every few of them
-    CDC(launch_cd_diag(V, nsig, d, s));
+    CDC(launch_cd_diag(V, nsig, d, bmax, s));
     CdState hs{0, 0, 0.0};
     int poll = kCdPollFirst;
     for (int k = 0; k <= max_vectors;) {
         const int kend = std::min(k + poll, max_vectors + 1);
-        for (; k < kend; ++k) CDC(launch_cd_step(V, nsig, Bc, d, piv, delta, k, max_vectors, st, s));
+        for (; k < kend; ++k) CDC(launch_cd_step(V, nsig, Bc, d, bmax, piv, delta, k, max_vectors, st, s));
         CDC(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s));
         CDC(hipStreamSynchronize(s));
         if (hs.done) break;

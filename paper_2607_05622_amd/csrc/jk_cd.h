@@ -54,14 +54,15 @@ struct CdScatterArgs {
     int nu[4];                   // user functions of the four shells
 };
 hipError_t launch_cd_scatter(const CdScatterArgs& a, hipStream_t s);
-// d[i] = V[i][i]
-hipError_t launch_cd_diag(const double* V, long long n, double* d, hipStream_t s);
-// step k (n > 0): pivot choice (one workgroup), then the new row Bc[k] and
-// the diagonal update; both do nothing once st->done is set.  At k = kcap
-// only the pivot choice runs, to tell a complete factor (done = 1) from one
-// that needs more than kcap vectors (done = 2).
-hipError_t launch_cd_step(const double* V, long long n, double* Bc, double* d, int* piv, double delta, int k,
-                          int kcap, CdState* st, hipStream_t s);
+// d[i] = V[i][i]; bmax[b] = the largest of d over block b of 256 (n > 0)
+hipError_t launch_cd_diag(const double* V, long long n, double* d, double* bmax, hipStream_t s);
+// step k (n > 0): pivot choice (one workgroup, from the block maxima bmax),
+// then the new row Bc[k], the diagonal update and its new block maxima;
+// both do nothing once st->done is set.  At k = kcap only the pivot choice
+// runs, to tell a complete factor (done = 1) from one that needs more than
+// kcap vectors (done = 2).
+hipError_t launch_cd_step(const double* V, long long n, double* Bc, double* d, double* bmax, int* piv, double delta,
+                          int k, int kcap, CdState* st, hipStream_t s);
 // B[q][m][n] = B[q][n][m] = Bc[q][i] for (m, n) = (pm[i], pn[i]), q < nvec
 // (B zeroed beforehand); pivots_out[q] = the user pair index of piv[q]
 hipError_t launch_cd_expand(const double* Bc, long long nsig, int nvec, const int* pm, const int* pn, int nf,

@@ -58,25 +58,49 @@ __global__ __launch_bounds__(256) void k_cd_scatter(CdScatterArgs a) {
     a.V[static_cast<long long>(cq) * a.nsig + cp] = v;
 }
 
-__global__ void k_cd_diag(const double* __restrict__ V, long long n, double* __restrict__ d) {
-    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) d[i] = V[i * n + i];
+// Largest value over a workgroup of 256 (every thread gets it).
+__device__ inline double block_max256(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return v;
+}
+
+// d[i] = V[i][i], and per block of 256 diagonals their largest (bmax)
+__global__ __launch_bounds__(256) void k_cd_diag(const double* __restrict__ V, long long n, double* __restrict__ d,
+                                                 double* __restrict__ bmax) {
+    __shared__ double red[4];
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    double v = -__DBL_MAX__;
+    if (i < n) {
+        v = V[i * n + i];
+        d[i] = v;
+    }
+    v = block_max256(v, red);
+    if (threadIdx.x == 0) bmax[blockIdx.x] = v;
 }
 
 // Pivot of step k (one workgroup of 1024): the largest remaining diagonal,
 // and among the diagonals within a relative 1e-10 of it the one of lowest
-// index.  If it is <= delta the factor is complete (done = 1, nvec = k); if
-// k has reached the caller's capacity the factor does not fit (done = 2).
+// index.  It reads only the per-block maxima of the remaining diagonals
+// (bmax, nb blocks of 256) and then one block: the first block whose
+// maximum reaches the threshold holds the first diagonal that does.  If the
+// largest is <= delta the factor is complete (done = 1, nvec = k); if k has
+// reached the caller's capacity the factor does not fit (done = 2).
 constexpr double kPivotTie = 1e-10;
 
-__global__ __launch_bounds__(1024) void k_cd_pivot(const double* __restrict__ d, long long n, double delta, int k,
-                                                   int kcap, int* __restrict__ piv, CdState* __restrict__ st) {
+__global__ __launch_bounds__(1024) void k_cd_pivot(const double* __restrict__ d, const double* __restrict__ bmax,
+                                                   long long n, double delta, int k, int kcap, int* __restrict__ piv,
+                                                   CdState* __restrict__ st) {
     if (st->done) return;
     __shared__ double smax[16];
     __shared__ int sidx[16];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nb = static_cast<int>((n + 255) / 256);
     double mx = -__DBL_MAX__;
-    for (long long i = tid; i < n; i += 1024) mx = fmax(mx, d[i]);
+    for (int b = tid; b < nb; b += 1024) mx = fmax(mx, bmax[b]);
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     if (lane == 0) smax[w] = mx;
     __syncthreads();
@@ -90,20 +114,34 @@ __global__ __launch_bounds__(1024) void k_cd_pivot(const double* __restrict__ d,
         return;
     }
     const double thr = (1.0 - kPivotTie) * mx;
-    int best = 0x7fffffff;
-    for (long long i = tid; i < n; i += 1024)
-        if (d[i] >= thr) {
-            best = static_cast<int>(i);
+    // first block whose maximum reaches thr
+    int fb = 0x7fffffff;
+    for (int b = tid; b < nb; b += 1024)
+        if (bmax[b] >= thr) {
+            fb = b;
             break;
         }
+    for (int o = 32; o > 0; o >>= 1) fb = min(fb, __shfl_xor(fb, o));
+    if (lane == 0) sidx[w] = fb;
+    __syncthreads();
+    fb = sidx[0];
+    for (int i = 1; i < 16; ++i) fb = min(fb, sidx[i]);
+    __syncthreads();
+    // first diagonal of that block that reaches thr (the first 256 threads)
+    int best = 0x7fffffff;
+    if (tid < 256) {
+        const long long i = static_cast<long long>(fb) * 256 + tid;
+        if (i < n && d[i] >= thr) best = tid;
+    }
     for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o));
     if (lane == 0) sidx[w] = best;
     __syncthreads();
     if (tid == 0) {
-        for (int i = 1; i < 16; ++i) best = min(best, sidx[i]);
+        for (int i = 1; i < 4; ++i) best = min(best, sidx[i]);
         best = min(best, sidx[0]);
-        piv[k] = best;
-        st->dp = d[best];
+        const int p = fb * 256 + best;
+        piv[k] = p;
+        st->dp = d[p];
     }
 }
 
@@ -112,10 +150,11 @@ __global__ __launch_bounds__(1024) void k_cd_pivot(const double* __restrict__ d,
 // update d[i] -= Bc[k][i]^2 with d[p] = 0.  The earlier rows' pivot entries
 // are staged in LDS 256 at a time.
 __global__ __launch_bounds__(256) void k_cd_column(const double* __restrict__ V, long long n, double* __restrict__ Bc,
-                                                   double* __restrict__ d, const int* __restrict__ piv, int k,
-                                                   const CdState* __restrict__ st) {
+                                                   double* __restrict__ d, double* __restrict__ bmax,
+                                                   const int* __restrict__ piv, int k, const CdState* __restrict__ st) {
     if (st->done) return;
     __shared__ double bp[256];
+    __shared__ double red[4];
     const int p = piv[k];
     const double dp = st->dp;
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
@@ -133,11 +172,15 @@ __global__ __launch_bounds__(256) void k_cd_column(const double* __restrict__ V,
         }
         __syncthreads();
     }
+    double dn = -__DBL_MAX__;
     if (in) {
         const double b = s / sqrt(dp);
         Bc[static_cast<long long>(k) * n + i] = b;
-        d[i] = i == p ? 0.0 : d[i] - b * b;
+        dn = i == p ? 0.0 : d[i] - b * b;
+        d[i] = dn;
     }
+    dn = block_max256(dn, red);
+    if (threadIdx.x == 0) bmax[blockIdx.x] = dn;
 }
 
 __global__ void k_cd_expand(const double* __restrict__ Bc, long long nsig, const int* __restrict__ pm,
@@ -185,17 +228,17 @@ hipError_t launch_cd_scatter(const CdScatterArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cd_diag(const double* V, long long n, double* d, hipStream_t s) {
+hipError_t launch_cd_diag(const double* V, long long n, double* d, double* bmax, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cd_diag, dim3(blocks_of(n, 256)), dim3(256), 0, s, V, n, d);
+    hipLaunchKernelGGL(k_cd_diag, dim3(blocks_of(n, 256)), dim3(256), 0, s, V, n, d, bmax);
     return hipGetLastError();
 }
 
-hipError_t launch_cd_step(const double* V, long long n, double* Bc, double* d, int* piv, double delta, int k,
-                          int kcap, CdState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cd_pivot, dim3(1), dim3(1024), 0, s, d, n, delta, k, kcap, piv, st);
+hipError_t launch_cd_step(const double* V, long long n, double* Bc, double* d, double* bmax, int* piv, double delta,
+                          int k, int kcap, CdState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cd_pivot, dim3(1), dim3(1024), 0, s, d, bmax, n, delta, k, kcap, piv, st);
     if (k >= kcap) return hipGetLastError();
-    hipLaunchKernelGGL(k_cd_column, dim3(blocks_of(n, 256)), dim3(256), 0, s, V, n, Bc, d, piv, k, st);
+    hipLaunchKernelGGL(k_cd_column, dim3(blocks_of(n, 256)), dim3(256), 0, s, V, n, Bc, d, bmax, piv, k, st);
     return hipGetLastError();
 }
 
