@@ -346,9 +346,10 @@ int jk_cd_factor(jk_basis_t h, double delta, double screen_tol, int32_t max_vect
  *   K[x] = sum_Q (B_Q U[x]) (B_Q V[x])^T
  * Device pointers: B [nvec][nf][nf] symmetric (as jk_cd_factor writes it),
  * U and V [nd][nf][r] row-major, J and K [nd][nf][nf] (overwritten; either
- * may be NULL, not both).  Asynchronous on stream; scratch of
- * nd nf^2 + 2 g nf nvec r + O(nf^2 + nvec nd) doubles is taken and released
- * on it, g the densities whose half-transforms B_Q U, B_Q V share 16 GB.  JK_EINVAL for bad sizes or NULL inputs, JK_ENOMEM when the
+ * may be NULL, not both).  Asynchronous on stream; scratch is taken and
+ * released on it: for J, nd nf^2 + (ceil(nf^2 / 4096) + 1) nvec nd
+ * doubles; for K, 2 g nf (nvec + 1) r + ceil(nvec r / 1024) nf^2 doubles,
+ * g the densities whose half-transforms B_Q U, B_Q V share 16 GB.  JK_EINVAL for bad sizes or NULL inputs, JK_ENOMEM when the
  * scratch cannot be allocated. */
 int jk_cd_jk(int32_t nf, int32_t nvec, const double* B, int32_t nd, int32_t r, const double* U, const double* V,
              double* J, double* K, void* stream);
