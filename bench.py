@@ -18,6 +18,12 @@ the roofline entry.  Quartet counts are those the whole screen kept, counted
 on the device.  The CPU baseline times the oracle on strided samples of bra
 shell pairs on all host cores and on one, scales each by the kept-quartet
 fraction, and checks sampled blocks of the timed GPU results against it.
+
+Beside the headline the line carries one forward edge of the Laplace
+cascade ("laplace_edge") and the Cholesky-factor J/K of 40 rank-40
+densities on the 620- and 312-AO bases against the direct build of the
+same densities ("cd", "cd.medium"): the factor's time and rank, J/K per
+call, their accuracy and the products' fraction of the FP64 peak.
 """
 from __future__ import annotations
 
